@@ -1,0 +1,185 @@
+"""Index-algebra oracle: A Mathematics of Arrays (MoA) and the psi-calculus.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): plain, slow Python that
+states the definitions of Ch. 2 ("Indexing and Shapes", the operator summary
+figure) and the psi Correspondence Theorem (Ch. 4, Def. psi_corr) directly,
+so that the printed worked examples of the paper and the product's lowering
+layer can be checked against them.  Arrays are ``MArray(shape, ravel)`` --
+the first of the two equivalent descriptions of an array in Ch. 2 -- with a
+row-major layout.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Sequence, Tuple
+
+
+def pi(v: Sequence[int]) -> int:
+    """Product of the items of a vector; pi of the empty vector is 1."""
+    out = 1
+    for x in v:
+        out *= int(x)
+    return out
+
+
+def iota(n: int) -> List[int]:
+    return list(range(int(n)))
+
+
+def take(k: int, v: Sequence[int]) -> List[int]:
+    """k >= 0: first k items; k < 0: last |k| items."""
+    v = list(v)
+    return v[:k] if k >= 0 else v[len(v) + k:]
+
+
+def drop(k: int, v: Sequence[int]) -> List[int]:
+    """k >= 0: all but the first k items; k < 0: all but the last |k| items."""
+    v = list(v)
+    return v[k:] if k >= 0 else v[:len(v) + k]
+
+
+def rotate(k: int, v: Sequence[int]) -> List[int]:
+    """k theta v: (k drop v) cat (k take v) for k >= 0, else (k take v) cat (k drop v)."""
+    if k >= 0:
+        return drop(k, v) + take(k, v)
+    return take(k, v) + drop(k, v)
+
+
+def gamma(shape: Sequence[int], idx: Sequence[int]) -> int:
+    """Row-major offset by the recurrence x_0 = p_0, x_j = x_{j-1} s_j + p_j (Def. gammadef)."""
+    if len(idx) == 0:
+        return 0
+    x = int(idx[0])
+    for j in range(1, len(idx)):
+        x = x * int(shape[j]) + int(idx[j])
+    return x
+
+
+def gamma_col(shape: Sequence[int], idx: Sequence[int]) -> int:
+    """Column-major offset: gamma on the reversed shape and index."""
+    return gamma(list(reversed(shape)), list(reversed(idx)))
+
+
+def gamma_inv(shape: Sequence[int], off: int) -> List[int]:
+    """gamma' : offset -> row-major index of an array of the given shape."""
+    idx = [0] * len(shape)
+    for j in range(len(shape) - 1, -1, -1):
+        s = int(shape[j])
+        idx[j] = off % s
+        off //= s
+    return idx
+
+
+def indices(shape: Sequence[int]):
+    """All full indices of an array of this shape, in lexical order."""
+    for off in range(pi(shape)):
+        yield gamma_inv(shape, off)
+
+
+@dataclass
+class MArray:
+    shape: List[int]
+    ravel: List
+
+    def __post_init__(self):
+        self.shape = [int(s) for s in self.shape]
+        self.ravel = list(self.ravel)
+        if len(self.ravel) != pi(self.shape):
+            raise ValueError("ravel length does not match the shape")
+
+    @property
+    def dim(self) -> int:
+        return len(self.shape)
+
+
+def psi(p: Sequence[int], A: MArray):
+    """p psi A.  Full index -> the item; partial index of length k -> the
+    sub-array of shape (k drop shape) whose items are (p cat q) psi A."""
+    p = list(p)
+    if len(p) > A.dim:
+        raise IndexError("index longer than the dimensionality")
+    for pj, sj in zip(p, A.shape):
+        if not 0 <= pj < sj:
+            raise IndexError("index out of range")
+    if len(p) == A.dim:
+        return A.ravel[gamma(A.shape, p)]
+    sub = drop(len(p), A.shape)
+    return MArray(sub, [A.ravel[gamma(A.shape, p + q)] for q in indices(sub)])
+
+
+def reshape(shape: Sequence[int], A: MArray) -> MArray:
+    """shape rho^ A: fill the new shape from the ravel in order, wrapping to the
+    start of the ravel when the new array is larger (Ch. 5, "The Importance of
+    the Array's Shape")."""
+    n = pi(shape)
+    src = A.ravel
+    if n and not src:
+        raise ValueError("cannot reshape an empty array into a non-empty one")
+    return MArray(list(shape), [src[i % len(src)] for i in range(n)])
+
+
+def transpose(A: MArray, perm: Sequence[int] | None = None) -> MArray:
+    """Generalized transpose: i psi (t transpose A) = i[t] psi A.  The shape of
+    the result satisfies shape[t[k]] = shape_A[k].  perm=None reverses the axes
+    (the ordinary 2-D transpose)."""
+    t = list(range(A.dim))[::-1] if perm is None else [int(v) for v in perm]
+    if sorted(t) != list(range(A.dim)):
+        raise ValueError("not a permutation")
+    shape = [0] * A.dim
+    for k in range(A.dim):
+        shape[t[k]] = A.shape[k]
+    out = []
+    for i in indices(shape):
+        out.append(psi([i[t[k]] for k in range(A.dim)], A))
+    return MArray(shape, out)
+
+
+def reverse(A: MArray) -> MArray:
+    """Phi A: reversal along axis 0."""
+    s0 = A.shape[0]
+    sub = pi(A.shape[1:])
+    out = []
+    for i in range(s0):
+        base = (s0 - 1 - i) * sub
+        out.extend(A.ravel[base:base + sub])
+    return MArray(A.shape, out)
+
+
+def take_array(k: int, A: MArray) -> MArray:
+    """k take A along axis 0 (0 <= k <= s_0)."""
+    sub = pi(A.shape[1:])
+    return MArray([k] + A.shape[1:], A.ravel[:k * sub])
+
+
+def rotate_array(k: int, A: MArray) -> MArray:
+    """Rotate A along axis 0 by k: <i> psi result = <(i + k) mod s_0> psi A."""
+    s0 = A.shape[0]
+    sub = pi(A.shape[1:])
+    out = []
+    for i in range(s0):
+        base = ((i + k) % s0) * sub
+        out.extend(A.ravel[base:base + sub])
+    return MArray(A.shape, out)
+
+
+def pct(shape: Sequence[int], j: Sequence[int]) -> Tuple[int, int]:
+    """psi Correspondence Theorem (Def. psi_corr): the ravel of j psi xi is the
+    contiguous run starting at gamma(j; (tau j) take shape) * pi((tau j) drop
+    shape) of length pi((tau j) drop shape).  Returns (start, length)."""
+    k = len(j)
+    length = pi(drop(k, shape))
+    return gamma(take(k, shape), j) * length, length
+
+
+def hyper(A: MArray) -> MArray:
+    """The hyper-cube view <2 2 ... 2> rho^ A of an array with 2^d items."""
+    n = len(A.ravel)
+    d = n.bit_length() - 1
+    if 1 << d != n:
+        raise ValueError("not a power of two")
+    return reshape([2] * d, A)
+
+
+def reshape_transpose(A: MArray, r: int, c: int) -> MArray:
+    """<r c> rho^ (transpose (<r c> rho^ A))  (Ch. 3, Eq. abstract)."""
+    return reshape([r, c], transpose(reshape([r, c], A)))
