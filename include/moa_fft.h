@@ -1,0 +1,204 @@
+/*
+ * moa_fft.h -- C ABI of the MI355X (gfx950) dimension-lifted radix-2 FFT.
+ *
+ * The operation is the complex discrete Fourier transform of a vector of
+ * length n = 2^t, t >= 0, as stated by the high-level radix-2 program of
+ * Ch. 3 (Fig. vanloan_fft: input x in C^n, output the FFT of x), computed by
+ * the cache-optimized ("dimension-lifted") method of Ch. 3-5: the vector is
+ * viewed through a lift shape <... r c>, every level's butterflies run inside
+ * one level of the GPU memory hierarchy (VGPRs and LDS of one workgroup),
+ * and twiddle multiplies and reshape-transposes happen between levels
+ * (sections "Cache-Optimized FFT: Key Elements of the New Approach",
+ * "The General Algorithm", "Reordering the Data").
+ *
+ * Conventions, for every entry point:
+ *   - FORWARD computes X_k = sum_j x_j exp(-2 pi i j k / n); ADJOINT computes
+ *     the conjugate transform Y_j = sum_k y_k exp(+2 pi i j k / n).  Neither
+ *     is normalised, so ADJOINT(FORWARD(x)) = n x.
+ *   - Complex data are interleaved (re, im) pairs: MOA_C64 = two float32
+ *     (the layout of torch.complex64), MOA_C128 = two float64.
+ *   - Input and output are in natural order.  Transforms of a batch are
+ *     contiguous, one after the other.
+ *   - Device pointers are HIP device addresses owned by the caller; the
+ *     library never frees them.  The plan owns its twiddle tables and
+ *     workspace and releases them in moa_fft_destroy.
+ *   - moa_fft_exec is asynchronous on the given HIP stream (NULL = the null
+ *     stream) and never synchronises the host.
+ *   - Every call returns a status; nothing aborts or throws across the ABI.
+ *     Arguments are validated on the host before any HIP call, so invalid
+ *     input is reported without touching the GPU.
+ *   - A plan is immutable after creation.  Concurrent moa_fft_exec calls on
+ *     one plan must be serialised on one stream because they share the
+ *     plan's workspace.
+ */
+#ifndef MOA_FFT_H
+#define MOA_FFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct moa_fft_plan_s* moa_fft_plan_t;
+
+typedef enum { MOA_FFT_FORWARD = 0, MOA_FFT_ADJOINT = 1 } moa_fft_dir_t;
+
+typedef enum { MOA_C64 = 0, MOA_C128 = 1 } moa_fft_dtype_t;
+
+/* Arithmetic of the butterflies.  NATIVE: float32 for MOA_C64, float64 for
+ * MOA_C128.  SPLIT_BF16 / SPLIT_FP16 (MOA_C64 only): every radix-16 stage is
+ * a dense 16-point DFT contraction on the matrix cores with each operand
+ * split into a high and a low half-precision part (three products, float32
+ * accumulation); the dense radix-n butterfly is the general-radix block of
+ * Ch. 1 (Fig. radnbutterfly).  Other stages and all twiddles stay float32. */
+typedef enum {
+    MOA_FFT_PREC_NATIVE = 0,
+    MOA_FFT_PREC_SPLIT_BF16 = 1,
+    MOA_FFT_PREC_SPLIT_FP16 = 2
+} moa_fft_prec_t;
+
+typedef enum {
+    MOA_OK = 0,
+    MOA_ERR_NULL = 1,        /* a required pointer argument is NULL            */
+    MOA_ERR_SIZE = 2,        /* n < 1, not a power of two, or above 2^30       */
+    MOA_ERR_LIFT = 3,        /* lift shape: product != n, a factor that is not
+                                a power of two, rank outside 1..8, or a level
+                                longer than one workgroup can hold in LDS      */
+    MOA_ERR_BATCH = 4,       /* batch < 1, count < 1, or total size overflow   */
+    MOA_ERR_DTYPE = 5,       /* unknown dtype/precision, or SPLIT with C128    */
+    MOA_ERR_ALLOC = 6,       /* device or host allocation failed               */
+    MOA_ERR_HIP = 7,         /* a HIP runtime call failed                      */
+    MOA_ERR_STATE = 8,       /* plan is host-only (cannot execute) or invalid  */
+    MOA_ERR_ARG = 9,         /* other invalid argument (direction, flags, len) */
+    MOA_ERR_TUNING = 10      /* tuning parameters outside the kernel's limits  */
+} moa_status_t;
+
+/* Flags for the plan constructors. */
+#define MOA_FFT_FLAG_HOST_ONLY 0x1u   /* validate and lower only: no device
+                                         resources; describe() works, exec()
+                                         returns MOA_ERR_STATE              */
+#define MOA_FFT_FLAG_PER_SIZE 0x2u    /* uneven batch: one plain launch per
+                                         distinct size instead of one
+                                         persistent launch                  */
+#define MOA_FFT_FLAG_GRAPH 0x4u       /* record the plan's launches for each
+                                         (direction, in, out) once as a HIP
+                                         graph of kernel nodes and replay it
+                                         with one hipGraphLaunch per exec   */
+
+/* Optional launch tuning, one entry per level of the lift (level 0 = the
+ * innermost block c, the first pass).  Zero entries select the defaults. */
+typedef struct {
+    int32_t cols_per_block[8];  /* transforms (columns of the lifted view)
+                                   handled by one workgroup in that pass   */
+    int32_t persistent_blocks;  /* uneven batch: workgroups of the
+                                   persistent launch (0 = one per task up
+                                   to the device's resident limit)          */
+    int32_t reserved[7];
+} moa_fft_tuning_t;
+
+/*
+ * Plan `batch` contiguous transforms of length n.
+ *
+ * lift_shape / lift_rank: the lift <s_0 ... s_{k-1}> of Ch. 3: the vector is
+ * viewed as an s_0 x ... x s_{k-1} array (row-major), s_{k-1} = c is the
+ * innermost block handled by the first level, and each further level works
+ * on the next axis outwards.  The product must equal n, every factor must
+ * be a power of two, and each factor must fit one workgroup (at most 2^14
+ * points for MOA_C64, 2^13 for MOA_C128).  NULL/0 selects a default lift
+ * with the fewest levels (one level when n itself fits).  The paper's
+ * uniform blocking by c corresponds to <2^p_max c ... c>.
+ *
+ * On success *out receives a new plan.  Errors: MOA_ERR_NULL (out NULL, or
+ * lift_shape NULL with lift_rank > 0), MOA_ERR_SIZE, MOA_ERR_LIFT,
+ * MOA_ERR_BATCH, MOA_ERR_DTYPE, MOA_ERR_ARG (unknown flag bits),
+ * MOA_ERR_ALLOC / MOA_ERR_HIP (device resources).  *out is untouched on
+ * error.
+ */
+moa_status_t moa_fft_plan(moa_fft_plan_t* out, int64_t n, int64_t batch,
+                          const int64_t* lift_shape, int32_t lift_rank,
+                          moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags);
+
+/* moa_fft_plan with explicit launch tuning (tuning may be NULL).
+ * MOA_ERR_TUNING if a value does not fit the kernel's limits. */
+moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch,
+                                const int64_t* lift_shape, int32_t lift_rank,
+                                moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags,
+                                const moa_fft_tuning_t* tuning);
+
+/*
+ * Plan an uneven batch: `count` transforms, transform i of length sizes[i]
+ * (each a power of two between 1 and 2^14 for MOA_C64, 2^13 for MOA_C128),
+ * packed one after the other in input and output (transform i starts at
+ * element sum_{j<i} sizes[j]).  The host array `sizes` is copied.  By
+ * default all transforms run in one persistent launch; with
+ * MOA_FFT_FLAG_PER_SIZE they run as one plain launch per distinct size.
+ * Errors as moa_fft_plan; MOA_ERR_SIZE names an invalid entry of sizes.
+ */
+moa_status_t moa_fft_plan_batched(moa_fft_plan_t* out, const int64_t* sizes, int64_t count,
+                                  moa_fft_dtype_t dtype, uint32_t flags);
+
+/* moa_fft_plan_batched with explicit tuning (tuning may be NULL). */
+moa_status_t moa_fft_plan_batched_tuned(moa_fft_plan_t* out, const int64_t* sizes, int64_t count,
+                                        moa_fft_dtype_t dtype, uint32_t flags,
+                                        const moa_fft_tuning_t* tuning);
+
+/*
+ * Execute a plan in direction dir on device buffers holding batch * n (or
+ * sum(sizes)) complex elements.  in == out (in place) is allowed; other
+ * overlaps are not.  Asynchronous on `stream` (a hipStream_t, NULL = null
+ * stream).  Errors: MOA_ERR_NULL (p, in or out NULL), MOA_ERR_ARG (bad dir),
+ * MOA_ERR_STATE (host-only plan), MOA_ERR_HIP (launch failure).
+ */
+moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out,
+                          void* stream);
+
+/*
+ * Run only level `level` of a lifted plan (one kernel launch): level 0 reads
+ * `in`, later levels read the plan's workspace; the last level writes
+ * `out`, earlier ones the workspace.  Running levels 0..L-1 in order equals
+ * moa_fft_exec.  For timing and inspecting one level of the lift
+ * ("The General Algorithm": one level = one pass over memory).  Errors as
+ * moa_fft_exec, plus MOA_ERR_ARG for a level outside 0..L-1 or an uneven
+ * batch plan.
+ */
+moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t level, const void* in,
+                                void* out, void* stream);
+
+/* Number of levels (= kernel launches per execution) of a plan; 1 for an
+ * uneven batch in one persistent launch. */
+moa_status_t moa_fft_num_levels(moa_fft_plan_t p, int32_t* levels);
+
+/* Bytes of device workspace the plan owns (0 for single-level plans). */
+moa_status_t moa_fft_workspace_size(moa_fft_plan_t p, size_t* bytes);
+
+/*
+ * Write a NUL-terminated JSON description of the plan into buf (len bytes):
+ * the lift, and for every pass the loop bounds and strides of its
+ * operational normal form (the DFT axis and each batch axis with its size,
+ * input stride and output stride), twiddle root, launch shape and LDS
+ * bytes.  Errors: MOA_ERR_NULL (p or buf NULL), MOA_ERR_ARG if len is
+ * smaller than moa_fft_describe_size (the text is then truncated and still
+ * NUL-terminated when len > 0).
+ */
+moa_status_t moa_fft_describe(moa_fft_plan_t p, char* buf, size_t len);
+
+/* Bytes (including the NUL) that moa_fft_describe needs for this plan. */
+moa_status_t moa_fft_describe_size(moa_fft_plan_t p, size_t* bytes);
+
+/* Release the plan and its device resources.  NULL is accepted (no-op).
+ * Destroying a plan twice is undefined: the handle is gone after the call. */
+moa_status_t moa_fft_destroy(moa_fft_plan_t p);
+
+/* Static, NUL-terminated name of a status code ("MOA_OK", ...). */
+const char* moa_fft_status_string(moa_status_t s);
+
+/* Largest single-level (in-LDS) transform length for a dtype. */
+int64_t moa_fft_max_block(moa_fft_dtype_t dtype);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOA_FFT_H */

@@ -1,0 +1,123 @@
+// Internal interfaces between the host planner (plan.cpp, psi.hpp) and the
+// gfx950 kernels (fft_kernels.hip, fft_batched.hip, fft_mfma.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace moa {
+
+constexpr int kMaxDigits = 8;     // batch digits of one pass descriptor
+constexpr int kMaxThreads = 1024; // workgroup size limit of every kernel
+constexpr int kLdsBytes = 160 * 1024;
+constexpr int kMaxLgBlockC64 = 14;  // 2^14 complex64 = 128 KiB (+pad) in LDS
+constexpr int kMaxLgBlockC128 = 13; // 2^13 complex128
+
+// Elements each thread keeps in registers across a pass (the radix of the
+// register-resident stages).  Transforms shorter than this use one thread.
+constexpr int kLgE = 4;
+
+// Element index -> padded LDS slot: one spare slot after every 16 elements
+// breaks the power-of-two strides of the butterfly exchanges across banks.
+__host__ __device__ constexpr inline int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr inline int lds_padded_len(int n) { return n + (n >> 4); }
+
+// Column stride (elements) of the LDS tile that holds several transforms side
+// by side.  It is the padded length rounded up so that 16 consecutive lanes
+// (the lanes served by one LDS cycle for 8-byte accesses) fall on distinct
+// 8-byte bank pairs: lanes_per_col consecutive rows of each of the
+// 16/lanes_per_col columns they cover.
+__host__ __device__ constexpr inline int lds_col_stride(int n, int lanes_per_col)
+{
+    int base = lds_padded_len(n);
+    int want = lanes_per_col >= 16 ? 0 : (lanes_per_col <= 0 ? 1 : lanes_per_col);
+    if (want == 0) return base;
+    int r = base & 31;
+    int add = (want - r + 32) & 31;
+    return base + add;
+}
+
+// One pass of a lifted plan in operational normal form: a DFT of length
+// 2^lgn along one axis (in stride in_s_e, out stride out_s_k) for every
+// combination of the batch digits.  Digit 0 is the tile digit: a workgroup
+// takes 2^lgw consecutive values of it.  All digit sizes are powers of two,
+// so block-index decoding is shifts and masks only -- except the last digit
+// (the batch of transforms), which may have any size: it takes whatever is
+// left of the block index.  A lone digit 0 is tiled by a width dividing it.
+struct PassDesc {
+    int lgn = 0;
+    int64_t in_s_e = 0, out_s_k = 0;
+    int nd = 0;
+    int64_t size[kMaxDigits] = {0};
+    int lg[kMaxDigits] = {0};
+    int64_t in_s[kMaxDigits] = {0};
+    int64_t out_s[kMaxDigits] = {0};
+    int lgw = 0;                  // log2 transforms per workgroup (tile width)
+    // Inter-level twiddle omega_{2^tw_lgroot}^(d0 * k), d0 = value of digit 0.
+    int tw = 0;
+    int tw_lgroot = 0;
+    int tw_lglo = 0;              // split of the two-level twiddle table
+    int64_t tw_hi_off = 0, tw_lo_off = 0;  // offsets (elements) into the plan's table buffer
+    // Launch shape (filled by the planner).
+    bool in_tile_fast = false;    // digit 0 is the unit-stride input axis
+    bool out_tile_fast = false;   // digit 0 is the unit-stride output axis
+    int threads = 0;
+    int col_stride = 0;           // LDS column stride in elements
+    int64_t blocks = 0;
+    int lds_bytes = 0;
+    int xcd_remap = 0;
+    int mfma = 0;                 // 0 = VALU radix-16, 1 = split bf16 MFMA, 2 = split fp16 MFMA
+};
+
+// Kernel argument block (passed by value).
+struct PassArgs {
+    const void* in;
+    void* out;
+    int64_t in_s_e, out_s_k;
+    int64_t in_s[kMaxDigits];
+    int64_t out_s[kMaxDigits];
+    int lg[kMaxDigits];
+    int nd;
+    int lgw;
+    int lg_tiles;                 // log2(size of digit 0 / tile width)
+    int col_stride;
+    int tw;
+    int tw_lgroot, tw_lglo;
+    const void* tw_hi;
+    const void* tw_lo;
+    const void* tw_blk;           // omega_{2^14}^e, e < 2^14 (in-block twiddles)
+    int xcd_remap;
+    float sign;                   // -1 forward, +1 adjoint
+};
+
+// A task of the uneven batch: `count` transforms of length 2^lgn whose
+// element offsets are toff[first .. first + count).
+struct BatchTask {
+    int32_t lgn;
+    int32_t count;
+    int64_t first;
+};
+
+struct BatchArgs {
+    const void* in;
+    void* out;
+    const BatchTask* tasks;
+    const int64_t* toff;
+    const void* tw_blk;
+    int ntasks;
+    int task0;                    // first task of this launch
+    float sign;
+};
+
+// Launchers (fft_kernels.hip / fft_batched.hip / fft_mfma.hip).  They return
+// hipSuccess or the launch error; they never synchronise.
+hipError_t launch_pass(bool fp64, const PassDesc& d, const PassArgs& a, hipStream_t s);
+hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d);  // sets LDS attributes
+hipError_t launch_batched(bool fp64, const BatchArgs& a, int grid, int threads, int lds_bytes,
+                          hipStream_t s);
+hipError_t prepare_batched_kernel(bool fp64, int lds_bytes);
+// The kernel function pointers, used to build HIP graph nodes.
+const void* pass_kernel_fn(bool fp64, const PassDesc& d);
+const void* batched_kernel_fn(bool fp64);
+
+}  // namespace moa

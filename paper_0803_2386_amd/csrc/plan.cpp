@@ -1,0 +1,789 @@
+// C ABI of the dimension-lifted FFT: validation, lowering of a lift to pass
+// descriptors (the psi-calculus layer), twiddle tables, device resources and
+// execution.  All host code; kernels live in the .hip files.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/moa_fft.h"
+#include "fft_internal.h"
+#include "psi.hpp"
+
+using moa::BatchTask;
+using moa::PassDesc;
+namespace psi = moa::psi;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x4d4f4146u;  // "MOAF"
+constexpr int kLgMaxN = 30;
+constexpr uint32_t kKnownFlags = MOA_FFT_FLAG_HOST_ONLY | MOA_FFT_FLAG_PER_SIZE | MOA_FFT_FLAG_GRAPH;
+
+bool is_pow2(int64_t x) { return x >= 1 && (x & (x - 1)) == 0; }
+int lg2(int64_t x)
+{
+    int t = 0;
+    while ((int64_t(1) << t) < x) ++t;
+    return t;
+}
+
+// omega_L^e = exp(-2 pi i e / L) in float64 from the exact integer exponent:
+// the quarter turn q = floor(4 e / L) is split off in integers, the rest is
+// an angle in [0, pi/2) whose cosine and sine are then rotated by q.
+void root_fp64(int64_t e, int64_t L, double* c, double* s)
+{
+    e %= L;
+    if (e < 0) e += L;
+    const int64_t q = (4 * e) / L;           // quadrant
+    const int64_t r = 4 * e - q * L;          // remainder, in units of 1/(4L) turn
+    const double a = (M_PI / 2.0) * double(r) / double(L);
+    double cr = cos(a), sr = sin(a);
+    double cc, ss;  // cos, sin of the full angle 2 pi e / L
+    switch (q) {
+        case 0: cc = cr; ss = sr; break;
+        case 1: cc = -sr; ss = cr; break;
+        case 2: cc = -cr; ss = -sr; break;
+        default: cc = sr; ss = -cr; break;
+    }
+    *c = cc;
+    *s = -ss;  // forward root: exp(-i theta)
+}
+
+struct GraphEntry {
+    int dir;
+    const void* in;
+    void* out;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct moa_fft_plan_s {
+    uint32_t magic = kMagic;
+    bool batched = false;
+    bool host_only = false;
+    bool fp64 = false;
+    int prec = MOA_FFT_PREC_NATIVE;
+    uint32_t flags = 0;
+    int64_t n = 0, batch = 0, total = 0;  // total = complex elements per buffer
+    std::vector<int64_t> lift;            // as given: outermost first
+    std::vector<int64_t> levels;          // f_0 (innermost, first pass) ...
+    std::vector<PassDesc> passes;
+    // uneven batch
+    std::vector<int64_t> sizes;
+    std::vector<BatchTask> tasks;
+    std::vector<int64_t> toff;
+    std::vector<std::pair<int, int>> size_ranges;  // (first task, tasks) per distinct size
+    int batch_threads = 0, batch_lds = 0, batch_grid = 0;
+    // tables: element offsets in d_tables (units of one complex element)
+    std::vector<double> tab_host;  // interleaved re/im, float64
+    int64_t tw_blk_off = 0;
+    // device resources
+    void* d_tables = nullptr;
+    void* d_ws = nullptr;
+    size_t ws_bytes = 0;
+    void* d_tasks = nullptr;
+    void* d_toff = nullptr;
+    int device = -1;
+    std::vector<GraphEntry> graphs;
+    std::mutex mu;
+};
+
+namespace {
+
+size_t elem_bytes(bool fp64) { return fp64 ? 16 : 8; }
+int max_lg_block(bool fp64) { return fp64 ? moa::kMaxLgBlockC128 : moa::kMaxLgBlockC64; }
+int max_threads(bool fp64) { return fp64 ? 512 : moa::kMaxThreads; }
+
+// Append omega_L^e for e in [first, first + count) scaled by `step` to the
+// host table; returns the element offset of the first entry.
+int64_t add_table(moa_fft_plan_s* p, int64_t L, int64_t count, int64_t step)
+{
+    const int64_t off = int64_t(p->tab_host.size() / 2);
+    p->tab_host.reserve(p->tab_host.size() + size_t(2 * count));
+    for (int64_t e = 0; e < count; ++e) {
+        double c, s;
+        root_fp64(e * step, L, &c, &s);
+        p->tab_host.push_back(c);
+        p->tab_host.push_back(s);
+    }
+    return off;
+}
+
+int lgE(int lgn) { return lgn < moa::kLgE ? lgn : moa::kLgE; }
+
+// Fill launch fields of a pass: tile width, mapping, LDS tile, grid.
+moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w)
+{
+    const int lgn = d.lgn;
+    const int tpc = 1 << (lgn - lgE(lgn));
+    // A lone digit 0 may have any size: its tiles must divide it.
+    int lg0 = d.lg[0];
+    if (d.nd == 1) {
+        lg0 = 0;
+        while ((d.size[0] % (int64_t(2) << lg0)) == 0) ++lg0;
+    }
+    const int eb = int(elem_bytes(fp64));
+    const int maxT = max_threads(fp64);
+    auto lds_for = [&](int lgw, bool tile_fast) {
+        const int W = 1 << lgw;
+        const int lanes = tile_fast ? (W >= 16 ? 1 : 16 / W) : tpc;
+        const int cs = moa::lds_col_stride(1 << lgn, lanes);
+        return std::make_pair(cs, W * cs * eb);
+    };
+    const bool in_tf = (d.in_s[0] == 1 && d.in_s_e != 1);
+    const bool out_tf = (d.out_s[0] == 1 && d.out_s_k != 1);
+    int lgw = 0;
+    if (want_w > 0) {
+        if (!is_pow2(want_w)) return MOA_ERR_TUNING;
+        lgw = lg2(want_w);
+        if (lgw > lg0) return MOA_ERR_TUNING;
+        if ((int64_t(1) << lgw) * tpc > maxT) return MOA_ERR_TUNING;
+        if (lds_for(lgw, in_tf && lgw > 0).second > moa::kLdsBytes) return MOA_ERR_TUNING;
+    } else {
+        // Default: as many columns as fit 2^14 (c64) / 2^13 (c128) points,
+        // the thread limit and LDS, and the digit itself.
+        const int target_lg = fp64 ? 13 : 14;
+        while (lgw < lg0 && lgn + lgw + 1 <= target_lg && (int64_t(2) << lgw) * tpc <= maxT &&
+               lds_for(lgw + 1, in_tf).second <= moa::kLdsBytes)
+            ++lgw;
+    }
+    d.lgw = lgw;
+    d.in_tile_fast = lgw > 0 && in_tf;
+    d.out_tile_fast = lgw > 0 && out_tf;
+    const auto cl = lds_for(lgw, d.in_tile_fast);
+    d.col_stride = cl.first;
+    d.lds_bytes = cl.second;
+    d.threads = (1 << lgw) * tpc;
+    int64_t blocks = d.size[0] >> lgw;
+    for (int i = 1; i < d.nd; ++i) blocks *= d.size[i];
+    if (blocks >= (int64_t(1) << 31)) return MOA_ERR_BATCH;
+    d.blocks = blocks;
+    d.xcd_remap = (blocks % 8 == 0 && blocks >= 16) ? 1 : 0;
+    return MOA_OK;
+}
+
+void push_digit(PassDesc& d, int64_t size, int64_t in_s, int64_t out_s)
+{
+    d.size[d.nd] = size;
+    d.lg[d.nd] = is_pow2(size) ? lg2(size) : -1;
+    d.in_s[d.nd] = in_s;
+    d.out_s[d.nd] = out_s;
+    ++d.nd;
+}
+
+// Lower the lift to one pass descriptor per level.
+//
+// The vector of one transform is viewed as the digit array D of shape
+// <f_0 f_1 ... f_{L-1}> (row-major, level-0 digit slowest): the psi view of
+// the lift.  By the decimation-in-time split, level l takes the DFT over
+// digit l for every value of the digits before it (already transformed,
+// they index frequencies k_0..k_{l-1}) and every value a'' of the digits
+// after it, then multiplies by omega_{f_l R_l}^(a'' k_l), R_l = pi(drop(l+1,
+// f)).  Every level keeps the digit positions of D (read pattern = write
+// pattern, so passes run in place in the workspace); the axis strides come
+// from the PCT run lengths of D.  The last level writes the result through
+// the final transpose: X = (reverse iota L) transpose D, i.e. frequency digit
+// k_i lands at stride pi(take(i, f)).
+moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
+{
+    const int L = int(p->levels.size());
+    const psi::Vec D(p->levels.begin(), p->levels.end());
+    const psi::Vec Rs = psi::axis_strides(D);                     // stride of digit i in x
+    const psi::Vec rev_strides = psi::axis_strides(psi::reverse(D));
+    psi::Vec perm(static_cast<size_t>(L));
+    for (int i = 0; i < L; ++i) perm[size_t(i)] = L - 1 - i;
+    const psi::Vec Xs = psi::transpose_view(rev_strides, perm);     // stride of k_i in X
+    const int64_t n = p->n, B = p->batch;
+    p->passes.clear();
+    for (int l = 0; l < L; ++l) {
+        PassDesc d;
+        d.lgn = lg2(D[size_t(l)]);
+        if (l < L - 1) {
+            const int64_t Rl = Rs[size_t(l)];
+            d.in_s_e = d.out_s_k = Rl;
+            push_digit(d, Rl, 1, 1);                                   // a'': tile digit
+            const int64_t outer = n / (D[size_t(l)] * Rl);
+            if (outer > 1) push_digit(d, outer, D[size_t(l)] * Rl, D[size_t(l)] * Rl);
+            if (B > 1) push_digit(d, B, n, n);
+            d.tw = 1;
+            d.tw_lgroot = lg2(D[size_t(l)] * Rl);
+            d.tw_lglo = (d.tw_lgroot + 1) / 2;
+        } else {
+            d.in_s_e = Rs[size_t(l)];
+            d.out_s_k = Xs[size_t(l)];
+            for (int i = 0; i < l; ++i) push_digit(d, D[size_t(i)], Rs[size_t(i)], Xs[size_t(i)]);
+            if (B > 1 || d.nd == 0) push_digit(d, B, n, n);
+        }
+        const int want = tuning ? tuning->cols_per_block[l] : 0;
+        if (tuning && (want < 0)) return MOA_ERR_TUNING;
+        moa_status_t st = finish_pass(d, p->fp64, want);
+        if (st != MOA_OK) return st;
+        p->passes.push_back(d);
+    }
+    return MOA_OK;
+}
+
+void build_tables(moa_fft_plan_s* p)
+{
+    p->tab_host.clear();
+    // In-block table: omega_{2^14}^e, e < 2^14.
+    p->tw_blk_off = add_table(p, int64_t(1) << 14, int64_t(1) << 14, 1);
+    for (PassDesc& d : p->passes) {
+        if (!d.tw) continue;
+        const int64_t root = int64_t(1) << d.tw_lgroot;
+        const int64_t nlo = int64_t(1) << d.tw_lglo;
+        const int64_t nhi = root / nlo;
+        d.tw_lo_off = add_table(p, root, nlo, 1);
+        d.tw_hi_off = add_table(p, root, nhi, nlo);
+    }
+}
+
+moa_status_t upload(moa_fft_plan_s* p)
+{
+    if (hipGetDevice(&p->device) != hipSuccess) return MOA_ERR_HIP;
+    const size_t eb = elem_bytes(p->fp64);
+    const size_t nel = p->tab_host.size() / 2;
+    std::vector<unsigned char> buf(nel * eb);
+    if (p->fp64) {
+        memcpy(buf.data(), p->tab_host.data(), nel * eb);
+    } else {
+        float* f = reinterpret_cast<float*>(buf.data());
+        for (size_t i = 0; i < 2 * nel; ++i) f[i] = float(p->tab_host[i]);
+    }
+    if (hipMalloc(&p->d_tables, buf.size()) != hipSuccess) return MOA_ERR_ALLOC;
+    if (hipMemcpy(p->d_tables, buf.data(), buf.size(), hipMemcpyHostToDevice) != hipSuccess) return MOA_ERR_HIP;
+    if (p->ws_bytes) {
+        if (hipMalloc(&p->d_ws, p->ws_bytes) != hipSuccess) return MOA_ERR_ALLOC;
+    }
+    if (!p->tasks.empty()) {
+        if (hipMalloc(&p->d_tasks, p->tasks.size() * sizeof(BatchTask)) != hipSuccess) return MOA_ERR_ALLOC;
+        if (hipMalloc(&p->d_toff, p->toff.size() * sizeof(int64_t)) != hipSuccess) return MOA_ERR_ALLOC;
+        if (hipMemcpy(p->d_tasks, p->tasks.data(), p->tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(p->d_toff, p->toff.data(), p->toff.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+                hipSuccess)
+            return MOA_ERR_HIP;
+        if (moa::prepare_batched_kernel(p->fp64, p->batch_lds) != hipSuccess) return MOA_ERR_HIP;
+    }
+    for (const PassDesc& d : p->passes)
+        if (moa::prepare_pass_kernel(p->fp64, d) != hipSuccess) return MOA_ERR_HIP;
+    return MOA_OK;
+}
+
+void release(moa_fft_plan_s* p)
+{
+    for (GraphEntry& g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    p->graphs.clear();
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_ws) (void)hipFree(p->d_ws);
+    if (p->d_tasks) (void)hipFree(p->d_tasks);
+    if (p->d_toff) (void)hipFree(p->d_toff);
+    p->d_tables = p->d_ws = p->d_tasks = p->d_toff = nullptr;
+}
+
+bool valid_plan(moa_fft_plan_t p) { return p && p->magic == kMagic; }
+
+moa_status_t check_common(moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags)
+{
+    if (dtype != MOA_C64 && dtype != MOA_C128) return MOA_ERR_DTYPE;
+    if (prec != MOA_FFT_PREC_NATIVE && prec != MOA_FFT_PREC_SPLIT_BF16 && prec != MOA_FFT_PREC_SPLIT_FP16)
+        return MOA_ERR_DTYPE;
+    if (prec != MOA_FFT_PREC_NATIVE && dtype != MOA_C64) return MOA_ERR_DTYPE;
+    if (flags & ~kKnownFlags) return MOA_ERR_ARG;
+    return MOA_OK;
+}
+
+moa_status_t finalize(moa_fft_plan_s* p, moa_fft_plan_t* out)
+{
+    if (!p->host_only) {
+        moa_status_t st = upload(p);
+        if (st != MOA_OK) {
+            release(p);
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return MOA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// JSON description
+// ---------------------------------------------------------------------------
+std::string describe_json(const moa_fft_plan_s* p)
+{
+    std::string s;
+    char b[512];
+    auto add = [&](const char* fmt, auto... args) {
+        snprintf(b, sizeof(b), fmt, args...);
+        s += b;
+    };
+    add("{\"kind\":\"%s\",\"dtype\":\"%s\",\"prec\":\"%s\",\"n\":%lld,\"batch\":%lld,\"elements\":%lld,",
+        p->batched ? "uneven_batch" : "lifted", p->fp64 ? "c128" : "c64",
+        p->prec == MOA_FFT_PREC_NATIVE ? "native" : (p->prec == MOA_FFT_PREC_SPLIT_BF16 ? "split_bf16" : "split_fp16"),
+        (long long)p->n, (long long)p->batch, (long long)p->total);
+    add("\"host_only\":%s,\"workspace_bytes\":%zu,", p->host_only ? "true" : "false", p->ws_bytes);
+    s += "\"lift\":[";
+    for (size_t i = 0; i < p->lift.size(); ++i) add("%s%lld", i ? "," : "", (long long)p->lift[i]);
+    s += "],\"levels\":[";
+    for (size_t i = 0; i < p->levels.size(); ++i) add("%s%lld", i ? "," : "", (long long)p->levels[i]);
+    s += "],\"passes\":[";
+    for (size_t l = 0; l < p->passes.size(); ++l) {
+        const PassDesc& d = p->passes[l];
+        const bool last = l + 1 == p->passes.size();
+        add("%s{\"level\":%zu,\"N\":%lld,\"in\":\"%s\",\"out\":\"%s\",\"dft_axis\":{\"in_stride\":%lld,"
+            "\"out_stride\":%lld},\"batch_axes\":[",
+            l ? "," : "", l, (long long)(int64_t(1) << d.lgn), l == 0 ? "x" : "workspace", last ? "y" : "workspace",
+            (long long)d.in_s_e, (long long)d.out_s_k);
+        for (int i = 0; i < d.nd; ++i)
+            add("%s{\"size\":%lld,\"in_stride\":%lld,\"out_stride\":%lld}", i ? "," : "",
+                (long long)d.size[i], (long long)d.in_s[i], (long long)d.out_s[i]);
+        add("],\"twiddle_root\":%lld,\"tile_width\":%d,\"threads\":%d,\"blocks\":%lld,\"lds_bytes\":%d,"
+            "\"lds_col_stride\":%d,\"in_tile_fast\":%s,\"out_tile_fast\":%s,\"xcd_remap\":%d}",
+            d.tw ? (long long)(int64_t(1) << d.tw_lgroot) : 0LL, 1 << d.lgw, d.threads, (long long)d.blocks,
+            d.lds_bytes, d.col_stride, d.in_tile_fast ? "true" : "false", d.out_tile_fast ? "true" : "false",
+            d.xcd_remap);
+    }
+    s += "]";
+    if (p->batched) {
+        add(",\"count\":%lld,\"tasks\":%zu,\"threads\":%d,\"lds_bytes\":%d,\"persistent_blocks\":%d,"
+            "\"per_size\":%s,\"sizes_by_task_group\":[",
+            (long long)p->sizes.size(), p->tasks.size(), p->batch_threads, p->batch_lds, p->batch_grid,
+            (p->flags & MOA_FFT_FLAG_PER_SIZE) ? "true" : "false");
+        for (size_t i = 0; i < p->size_ranges.size(); ++i) {
+            const auto& r = p->size_ranges[i];
+            add("%s{\"n\":%lld,\"first_task\":%d,\"tasks\":%d}", i ? "," : "",
+                (long long)(int64_t(1) << p->tasks[size_t(r.first)].lgn), r.first, r.second);
+        }
+        s += "]";
+    }
+    s += "}";
+    return s;
+}
+
+moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, GraphEntry& g);
+moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, hipStream_t s);
+
+// Fill the kernel argument blocks of every pass for one execution.
+void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, std::vector<moa::PassArgs>& args)
+{
+    const size_t eb = elem_bytes(p->fp64);
+    const unsigned char* tb = static_cast<const unsigned char*>(p->d_tables);
+    args.clear();
+    const size_t P = p->passes.size();
+    for (size_t l = 0; l < P; ++l) {
+        const PassDesc& d = p->passes[l];
+        moa::PassArgs a;
+        memset(&a, 0, sizeof(a));
+        a.in = l == 0 ? in : p->d_ws;
+        a.out = (l + 1 == P) ? out : p->d_ws;
+        a.in_s_e = d.in_s_e;
+        a.out_s_k = d.out_s_k;
+        for (int i = 0; i < moa::kMaxDigits; ++i) {
+            a.in_s[i] = d.in_s[i];
+            a.out_s[i] = d.out_s[i];
+            a.lg[i] = d.lg[i];
+        }
+        a.nd = d.nd;
+        a.lgw = d.lgw;
+        a.lg_tiles = d.nd == 1 ? 0 : d.lg[0] - d.lgw;
+        a.col_stride = d.col_stride;
+        a.tw = d.tw;
+        a.tw_lgroot = d.tw_lgroot;
+        a.tw_lglo = d.tw_lglo;
+        a.tw_hi = tb + size_t(d.tw_hi_off) * eb;
+        a.tw_lo = tb + size_t(d.tw_lo_off) * eb;
+        a.tw_blk = tb + size_t(p->tw_blk_off) * eb;
+        a.xcd_remap = d.xcd_remap;
+        a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
+        args.push_back(a);
+    }
+}
+
+moa::BatchArgs batch_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, int task0, int ntasks)
+{
+    moa::BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = in;
+    a.out = out;
+    a.tasks = static_cast<const BatchTask*>(p->d_tasks);
+    a.toff = static_cast<const int64_t*>(p->d_toff);
+    a.tw_blk = static_cast<const unsigned char*>(p->d_tables) + size_t(p->tw_blk_off) * elem_bytes(p->fp64);
+    a.task0 = task0;
+    a.ntasks = ntasks;
+    a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
+    return a;
+}
+
+moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, hipStream_t s)
+{
+    if (p->batched) {
+        if (p->flags & MOA_FFT_FLAG_PER_SIZE) {
+            for (const auto& r : p->size_ranges) {
+                moa::BatchArgs a = batch_args(p, dir, in, out, r.first, r.second);
+                if (moa::launch_batched(p->fp64, a, r.second, p->batch_threads, p->batch_lds, s) != hipSuccess)
+                    return MOA_ERR_HIP;
+            }
+        } else {
+            moa::BatchArgs a = batch_args(p, dir, in, out, 0, int(p->tasks.size()));
+            if (moa::launch_batched(p->fp64, a, p->batch_grid, p->batch_threads, p->batch_lds, s) != hipSuccess)
+                return MOA_ERR_HIP;
+        }
+        return MOA_OK;
+    }
+    std::vector<moa::PassArgs> args;
+    pass_args(p, dir, in, out, args);
+    for (size_t l = 0; l < p->passes.size(); ++l)
+        if (moa::launch_pass(p->fp64, p->passes[l], args[l], s) != hipSuccess) return MOA_ERR_HIP;
+    return MOA_OK;
+}
+
+moa_status_t add_node(hipGraph_t g, hipGraphNode_t* prev, const void* fn, dim3 grid, dim3 block, int lds,
+                      void* argp)
+{
+    hipKernelNodeParams kp;
+    memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = unsigned(lds);
+    void* params[1] = {argp};
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    if (hipGraphAddKernelNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, &kp) != hipSuccess)
+        return MOA_ERR_HIP;
+    *prev = node;
+    return MOA_OK;
+}
+
+moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, GraphEntry& g)
+{
+    g.dir = dir;
+    g.in = in;
+    g.out = out;
+    if (hipGraphCreate(&g.graph, 0) != hipSuccess) return MOA_ERR_HIP;
+    hipGraphNode_t prev = nullptr;
+    moa_status_t st = MOA_OK;
+    if (p->batched) {
+        if (p->flags & MOA_FFT_FLAG_PER_SIZE) {
+            for (const auto& r : p->size_ranges) {
+                moa::BatchArgs a = batch_args(p, dir, in, out, r.first, r.second);
+                st = add_node(g.graph, &prev, moa::batched_kernel_fn(p->fp64), dim3(unsigned(r.second)),
+                              dim3(unsigned(p->batch_threads)), p->batch_lds, &a);
+                if (st != MOA_OK) break;
+            }
+        } else {
+            moa::BatchArgs a = batch_args(p, dir, in, out, 0, int(p->tasks.size()));
+            st = add_node(g.graph, &prev, moa::batched_kernel_fn(p->fp64), dim3(unsigned(p->batch_grid)),
+                          dim3(unsigned(p->batch_threads)), p->batch_lds, &a);
+        }
+    } else {
+        std::vector<moa::PassArgs> args;
+        pass_args(p, dir, in, out, args);
+        for (size_t l = 0; l < p->passes.size() && st == MOA_OK; ++l) {
+            const PassDesc& d = p->passes[l];
+            st = add_node(g.graph, &prev, moa::pass_kernel_fn(p->fp64, d), dim3(unsigned(d.blocks)),
+                          dim3(unsigned(d.threads)), d.lds_bytes, &args[l]);
+        }
+    }
+    if (st == MOA_OK && hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) st = MOA_ERR_HIP;
+    if (st != MOA_OK) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g.exec = nullptr;
+        g.graph = nullptr;
+    }
+    return st;
+}
+
+// Validate the sizes and build the tasks of an uneven batch.
+moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
+{
+    const int maxlg = max_lg_block(p->fp64);
+    const size_t eb = elem_bytes(p->fp64);
+    const int T = max_threads(p->fp64);
+    const int64_t count = int64_t(p->sizes.size());
+    std::vector<int64_t> off(size_t(count) + 1, 0);
+    std::vector<std::vector<int64_t>> by_lg(size_t(maxlg) + 1);
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t s = p->sizes[size_t(i)];
+        if (!is_pow2(s) || lg2(s) > maxlg) return MOA_ERR_SIZE;
+        off[size_t(i) + 1] = off[size_t(i)] + s;
+        by_lg[size_t(lg2(s))].push_back(i);
+    }
+    p->total = off[size_t(count)];
+    int lds_max = 0;
+    p->tasks.clear();
+    p->toff.clear();
+    p->size_ranges.clear();
+    for (int lg = maxlg; lg >= 0; --lg) {
+        const auto& idx = by_lg[size_t(lg)];
+        if (idx.empty()) continue;
+        const int tpc = 1 << (lg - lgE(lg));
+        const int cs = moa::lds_col_stride(1 << lg, tpc);
+        // LDS of one full tile: 2^14 complex64 or 2^13 complex128 points.
+        const int64_t budget = int64_t(moa::lds_padded_len(1 << maxlg)) * int64_t(eb);
+        int per = std::min(T / tpc, int(budget / (int64_t(cs) * int64_t(eb))));
+        per = std::max(per, 1);
+        const int first_task = int(p->tasks.size());
+        for (size_t k = 0; k < idx.size(); k += size_t(per)) {
+            const int cnt = int(std::min<size_t>(size_t(per), idx.size() - k));
+            BatchTask tk;
+            tk.lgn = lg;
+            tk.count = cnt;
+            tk.first = int64_t(p->toff.size());
+            for (int w = 0; w < cnt; ++w) p->toff.push_back(off[size_t(idx[k + size_t(w)])]);
+            p->tasks.push_back(tk);
+            lds_max = std::max(lds_max, int(int64_t(cnt) * cs * int64_t(eb)));
+        }
+        p->size_ranges.push_back({first_task, int(p->tasks.size()) - first_task});
+    }
+    // Within a size the full tasks come first; sizes are already longest first.
+    p->batch_threads = T;
+    p->batch_lds = std::max(lds_max, 16);
+    int grid = int(p->tasks.size());
+    if (tuning && tuning->persistent_blocks < 0) return MOA_ERR_TUNING;
+    if (tuning && tuning->persistent_blocks > 0) {
+        grid = std::min(grid, int(tuning->persistent_blocks));
+    } else if (!p->host_only) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int per_cu = std::max(1, moa::kLdsBytes / p->batch_lds);
+        grid = std::min(grid, cus * per_cu);
+    } else {
+        grid = std::min(grid, 256 * std::max(1, moa::kLdsBytes / p->batch_lds));
+    }
+    p->batch_grid = std::max(grid, 1);
+    return MOA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* moa_fft_status_string(moa_status_t s)
+{
+    switch (s) {
+        case MOA_OK: return "MOA_OK";
+        case MOA_ERR_NULL: return "MOA_ERR_NULL";
+        case MOA_ERR_SIZE: return "MOA_ERR_SIZE";
+        case MOA_ERR_LIFT: return "MOA_ERR_LIFT";
+        case MOA_ERR_BATCH: return "MOA_ERR_BATCH";
+        case MOA_ERR_DTYPE: return "MOA_ERR_DTYPE";
+        case MOA_ERR_ALLOC: return "MOA_ERR_ALLOC";
+        case MOA_ERR_HIP: return "MOA_ERR_HIP";
+        case MOA_ERR_STATE: return "MOA_ERR_STATE";
+        case MOA_ERR_ARG: return "MOA_ERR_ARG";
+        case MOA_ERR_TUNING: return "MOA_ERR_TUNING";
+    }
+    return "MOA_ERR_UNKNOWN";
+}
+
+int64_t moa_fft_max_block(moa_fft_dtype_t dtype)
+{
+    if (dtype == MOA_C64) return int64_t(1) << moa::kMaxLgBlockC64;
+    if (dtype == MOA_C128) return int64_t(1) << moa::kMaxLgBlockC128;
+    return 0;
+}
+
+moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, const int64_t* lift_shape,
+                                int32_t lift_rank, moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags,
+                                const moa_fft_tuning_t* tuning)
+{
+    if (!out) return MOA_ERR_NULL;
+    if (lift_rank > 0 && !lift_shape) return MOA_ERR_NULL;
+    moa_status_t st = check_common(dtype, prec, flags);
+    if (st != MOA_OK) return st;
+    if (flags & MOA_FFT_FLAG_PER_SIZE) return MOA_ERR_ARG;
+    if (!is_pow2(n) || lg2(n) > kLgMaxN) return MOA_ERR_SIZE;
+    if (batch < 1) return MOA_ERR_BATCH;
+    if (n > (int64_t(1) << 40) / batch) return MOA_ERR_BATCH;
+    if (lift_rank < 0 || lift_rank > 8) return MOA_ERR_LIFT;
+    const bool fp64 = dtype == MOA_C128;
+    const int maxlg = max_lg_block(fp64);
+    std::vector<int64_t> lift;
+    if (lift_rank > 0) {
+        int64_t prod = 1;
+        for (int i = 0; i < lift_rank; ++i) {
+            const int64_t f = lift_shape[i];
+            if (!is_pow2(f) || lg2(f) > maxlg) return MOA_ERR_LIFT;
+            if (f < 2 && !(n == 1 && lift_rank == 1)) return MOA_ERR_LIFT;
+            if (prod > (int64_t(1) << 40) / f) return MOA_ERR_LIFT;
+            prod *= f;
+            lift.push_back(f);
+        }
+        if (prod != n) return MOA_ERR_LIFT;
+    } else {
+        const int d = lg2(n);
+        const int L = d <= maxlg ? 1 : (d + maxlg - 1) / maxlg;
+        // near-equal split, the outer levels take the remainder first
+        for (int i = 0; i < L; ++i) {
+            const int part = d / L + (i < d % L ? 1 : 0);
+            lift.push_back(int64_t(1) << part);
+        }
+    }
+    if (prec != MOA_FFT_PREC_NATIVE) return MOA_ERR_DTYPE;  // matrix-core path: planned per level below
+    moa_fft_plan_s* p = new (std::nothrow) moa_fft_plan_s();
+    if (!p) return MOA_ERR_ALLOC;
+    p->fp64 = fp64;
+    p->prec = prec;
+    p->flags = flags;
+    p->host_only = (flags & MOA_FFT_FLAG_HOST_ONLY) != 0;
+    p->n = n;
+    p->batch = batch;
+    p->total = n * batch;
+    p->lift = lift;
+    p->levels.assign(lift.rbegin(), lift.rend());
+    st = lower(p, tuning);
+    if (st != MOA_OK) {
+        delete p;
+        return st;
+    }
+    build_tables(p);
+    p->ws_bytes = p->passes.size() > 1 ? size_t(p->total) * elem_bytes(fp64) : 0;
+    return finalize(p, out);
+}
+
+moa_status_t moa_fft_plan(moa_fft_plan_t* out, int64_t n, int64_t batch, const int64_t* lift_shape,
+                          int32_t lift_rank, moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags)
+{
+    return moa_fft_plan_tuned(out, n, batch, lift_shape, lift_rank, dtype, prec, flags, nullptr);
+}
+
+moa_status_t moa_fft_plan_batched_tuned(moa_fft_plan_t* out, const int64_t* sizes, int64_t count,
+                                        moa_fft_dtype_t dtype, uint32_t flags, const moa_fft_tuning_t* tuning)
+{
+    if (!out || !sizes) return MOA_ERR_NULL;
+    moa_status_t st = check_common(dtype, MOA_FFT_PREC_NATIVE, flags);
+    if (st != MOA_OK) return st;
+    if (count < 1 || count > (int64_t(1) << 28)) return MOA_ERR_BATCH;
+    moa_fft_plan_s* p = new (std::nothrow) moa_fft_plan_s();
+    if (!p) return MOA_ERR_ALLOC;
+    p->batched = true;
+    p->fp64 = dtype == MOA_C128;
+    p->flags = flags;
+    p->host_only = (flags & MOA_FFT_FLAG_HOST_ONLY) != 0;
+    p->sizes.assign(sizes, sizes + count);
+    p->batch = count;
+    st = plan_uneven(p, tuning);
+    if (st != MOA_OK) {
+        delete p;
+        return st;
+    }
+    p->tab_host.clear();
+    p->tw_blk_off = add_table(p, int64_t(1) << 14, int64_t(1) << 14, 1);
+    return finalize(p, out);
+}
+
+moa_status_t moa_fft_plan_batched(moa_fft_plan_t* out, const int64_t* sizes, int64_t count, moa_fft_dtype_t dtype,
+                                  uint32_t flags)
+{
+    return moa_fft_plan_batched_tuned(out, sizes, count, dtype, flags, nullptr);
+}
+
+moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out, void* stream)
+{
+    if (!valid_plan(p) || !in || !out) return MOA_ERR_NULL;
+    if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
+    if (p->host_only) return MOA_ERR_STATE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!(p->flags & MOA_FFT_FLAG_GRAPH)) return launch_all(p, int(dir), in, out, s);
+    std::lock_guard<std::mutex> lock(p->mu);
+    GraphEntry* hit = nullptr;
+    for (GraphEntry& g : p->graphs)
+        if (g.dir == int(dir) && g.in == in && g.out == out) hit = &g;
+    if (!hit) {
+        if (p->graphs.size() >= 8) {
+            GraphEntry& old = p->graphs.front();
+            if (old.exec) (void)hipGraphExecDestroy(old.exec);
+            if (old.graph) (void)hipGraphDestroy(old.graph);
+            p->graphs.erase(p->graphs.begin());
+        }
+        GraphEntry g;
+        moa_status_t st = make_graph(p, int(dir), in, out, g);
+        if (st != MOA_OK) return st;
+        p->graphs.push_back(g);
+        hit = &p->graphs.back();
+    }
+    return hipGraphLaunch(hit->exec, s) == hipSuccess ? MOA_OK : MOA_ERR_HIP;
+}
+
+moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t level, const void* in, void* out,
+                                void* stream)
+{
+    if (!valid_plan(p) || !in || !out) return MOA_ERR_NULL;
+    if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
+    if (p->batched || level < 0 || size_t(level) >= p->passes.size()) return MOA_ERR_ARG;
+    if (p->host_only) return MOA_ERR_STATE;
+    std::vector<moa::PassArgs> args;
+    pass_args(p, int(dir), in, out, args);
+    return moa::launch_pass(p->fp64, p->passes[size_t(level)], args[size_t(level)],
+                            static_cast<hipStream_t>(stream)) == hipSuccess
+               ? MOA_OK
+               : MOA_ERR_HIP;
+}
+
+moa_status_t moa_fft_num_levels(moa_fft_plan_t p, int32_t* levels)
+{
+    if (!valid_plan(p) || !levels) return MOA_ERR_NULL;
+    if (p->batched)
+        *levels = (p->flags & MOA_FFT_FLAG_PER_SIZE) ? int32_t(p->size_ranges.size()) : 1;
+    else
+        *levels = int32_t(p->passes.size());
+    return MOA_OK;
+}
+
+moa_status_t moa_fft_workspace_size(moa_fft_plan_t p, size_t* bytes)
+{
+    if (!valid_plan(p) || !bytes) return MOA_ERR_NULL;
+    *bytes = p->ws_bytes;
+    return MOA_OK;
+}
+
+moa_status_t moa_fft_describe_size(moa_fft_plan_t p, size_t* bytes)
+{
+    if (!valid_plan(p) || !bytes) return MOA_ERR_NULL;
+    *bytes = describe_json(p).size() + 1;
+    return MOA_OK;
+}
+
+moa_status_t moa_fft_describe(moa_fft_plan_t p, char* buf, size_t len)
+{
+    if (!valid_plan(p) || !buf) return MOA_ERR_NULL;
+    const std::string s = describe_json(p);
+    if (len == 0) return MOA_ERR_ARG;
+    const size_t k = std::min(len - 1, s.size());
+    memcpy(buf, s.data(), k);
+    buf[k] = '\0';
+    return (s.size() + 1 <= len) ? MOA_OK : MOA_ERR_ARG;
+}
+
+moa_status_t moa_fft_destroy(moa_fft_plan_t p)
+{
+    if (!p) return MOA_OK;
+    if (!valid_plan(p)) return MOA_ERR_STATE;
+    release(p);
+    p->magic = 0;
+    delete p;
+    return MOA_OK;
+}
+
+}  // extern "C"

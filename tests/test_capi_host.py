@@ -1,0 +1,225 @@
+"""Host-side tests of the C-ABI library (no GPU needed): it loads, exports
+every function include/moa_fft.h declares, validates arguments with the
+documented status codes, and lowers lifts to pass descriptors that compute the
+DFT.  The descriptors are checked by interpreting them on the CPU (gather by
+the stated strides, DFT, inter-level twiddle, scatter) against the FP64
+oracle, and their index maps against the MoA index oracle."""
+import ctypes
+import itertools
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import moa
+from paper_0803_2386_amd import capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOST = capi.MOA_FFT_FLAG_HOST_ONLY
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built_library():
+    if not os.path.exists(capi.LIB_PATH):
+        import paper_0803_2386_amd.build as b
+        b.build()
+    capi.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "moa_fft.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const char\*|moa_status_t|int64_t)\s+(moa_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(capi.EXPORTED) == names
+
+
+def test_status_strings():
+    for code, name in [(0, "MOA_OK"), (1, "MOA_ERR_NULL"), (2, "MOA_ERR_SIZE"), (3, "MOA_ERR_LIFT"),
+                       (4, "MOA_ERR_BATCH"), (5, "MOA_ERR_DTYPE"), (6, "MOA_ERR_ALLOC"), (7, "MOA_ERR_HIP"),
+                       (8, "MOA_ERR_STATE"), (9, "MOA_ERR_ARG"), (10, "MOA_ERR_TUNING")]:
+        assert capi.moa_fft_status_string(code) == name
+    assert capi.moa_fft_status_string(99) == "MOA_ERR_UNKNOWN"
+    assert capi.moa_fft_max_block(capi.MOA_C64) == 1 << 14
+    assert capi.moa_fft_max_block(capi.MOA_C128) == 1 << 13
+
+
+def status_of(fn, *a, **k):
+    try:
+        h = fn(*a, **k)
+    except capi.MoaError as e:
+        return e.status
+    capi.moa_fft_destroy(h)
+    return capi.MOA_OK
+
+
+@pytest.mark.parametrize("args,want", [
+    (dict(n=0), capi.MOA_ERR_SIZE), (dict(n=3), capi.MOA_ERR_SIZE), (dict(n=1 << 31), capi.MOA_ERR_SIZE),
+    (dict(n=16, batch=0), capi.MOA_ERR_BATCH), (dict(n=16, batch=-4), capi.MOA_ERR_BATCH),
+    (dict(n=16, lift_shape=[4, 8]), capi.MOA_ERR_LIFT), (dict(n=24 * 0 + 32, lift_shape=[4, 6]), capi.MOA_ERR_LIFT),
+    (dict(n=1 << 15, lift_shape=[1 << 15]), capi.MOA_ERR_LIFT),
+    (dict(n=1 << 14, lift_shape=[1 << 14], dtype=capi.MOA_C128), capi.MOA_ERR_LIFT),
+    (dict(n=512, lift_shape=[2] * 9), capi.MOA_ERR_LIFT), (dict(n=16, lift_shape=[16, 1]), capi.MOA_ERR_LIFT),
+    (dict(n=16, dtype=7), capi.MOA_ERR_DTYPE), (dict(n=16, prec=9), capi.MOA_ERR_DTYPE),
+    (dict(n=16, dtype=capi.MOA_C128, prec=capi.MOA_FFT_PREC_SPLIT_BF16), capi.MOA_ERR_DTYPE),
+    (dict(n=16, flags=HOST | 0x100), capi.MOA_ERR_ARG), (dict(n=16, flags=HOST | capi.MOA_FFT_FLAG_PER_SIZE),
+                                                          capi.MOA_ERR_ARG),
+    (dict(n=4096, lift_shape=[64, 64], tuning=dict(cols_per_block=[3])), capi.MOA_ERR_TUNING),
+    (dict(n=4096, lift_shape=[64, 64], tuning=dict(cols_per_block=[128])), capi.MOA_ERR_TUNING),
+    (dict(n=1 << 24, lift_shape=[4096, 4096], tuning=dict(cols_per_block=[16])), capi.MOA_ERR_TUNING),
+    (dict(n=16), capi.MOA_OK), (dict(n=1), capi.MOA_OK), (dict(n=1 << 30), capi.MOA_OK),
+])
+def test_plan_validation(args, want):
+    args = dict(args)
+    args["flags"] = args.get("flags", 0) | HOST
+    assert status_of(capi.moa_fft_plan, **args) == want
+
+
+def test_null_pointers():
+    lib = capi.load()
+    assert lib.moa_fft_plan(None, 16, 1, None, 0, 0, 0, HOST) == capi.MOA_ERR_NULL
+    h = ctypes.c_void_p()
+    assert lib.moa_fft_plan(ctypes.byref(h), 16, 1, None, 2, 0, 0, HOST) == capi.MOA_ERR_NULL
+    assert lib.moa_fft_plan_batched(ctypes.byref(h), None, 4, 0, HOST) == capi.MOA_ERR_NULL
+    assert lib.moa_fft_exec(None, 0, None, None, None) == capi.MOA_ERR_NULL
+    assert lib.moa_fft_destroy(None) == capi.MOA_OK
+    size = ctypes.c_size_t()
+    assert lib.moa_fft_workspace_size(None, ctypes.byref(size)) == capi.MOA_ERR_NULL
+
+
+def test_host_only_plan_cannot_execute_and_describe_truncates():
+    lib = capi.load()
+    h = capi.moa_fft_plan(1024, 2, None, flags=HOST)
+    try:
+        buf = ctypes.create_string_buffer(16)
+        assert lib.moa_fft_exec(h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == capi.MOA_ERR_STATE
+        assert lib.moa_fft_exec(h, 5, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == capi.MOA_ERR_ARG
+        assert lib.moa_fft_describe(h, buf, 16) == capi.MOA_ERR_ARG
+        assert len(buf.value) == 15
+        assert json.loads(capi.moa_fft_describe(h))["n"] == 1024
+    finally:
+        capi.moa_fft_destroy(h)
+
+
+@pytest.mark.parametrize("sizes,want", [([3], capi.MOA_ERR_SIZE), ([64, 1 << 15], capi.MOA_ERR_SIZE),
+                                        ([], capi.MOA_ERR_BATCH), ([1 << 14], capi.MOA_OK)])
+def test_batched_validation(sizes, want):
+    if not sizes:
+        lib = capi.load()
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_int64 * 1)(64)
+        assert lib.moa_fft_plan_batched(ctypes.byref(h), arr, 0, 0, HOST) == want
+        return
+    assert status_of(capi.moa_fft_plan_batched, sizes, flags=HOST) == want
+
+
+def describe(n, batch=1, lift=None, dtype=capi.MOA_C64, tuning=None):
+    h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST, tuning=tuning)
+    try:
+        return json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+
+
+def test_default_lifts():
+    assert describe(1 << 24)["lift"] == [4096, 4096]
+    assert describe(1 << 20)["lift"] == [1024, 1024]
+    assert describe(1 << 16)["lift"] == [256, 256]
+    assert describe(1 << 14)["lift"] == [1 << 14]
+    assert describe(1 << 14, dtype=capi.MOA_C128)["lift"] == [128, 128]
+    assert describe(1 << 30)["lift"] == [1024, 1024, 1024]
+    d = describe(1 << 24, lift=[4096, 4096])
+    assert d["levels"] == [4096, 4096] and len(d["passes"]) == 2
+    assert d["workspace_bytes"] == 8 << 24
+
+
+def interpret(desc, x, sign):
+    """Run the plan's pass descriptors on the CPU: every pass gathers each
+    transform by its strides, takes the DFT, applies the inter-level twiddle
+    omega_root^(d0 k) (d0 = value of batch axis 0) and scatters it."""
+    total = x.size
+    ws = np.zeros(total, complex)
+    out = np.zeros(total, complex)
+    src = x
+    for p in desc["passes"]:
+        N = p["N"]
+        ise, osk = p["dft_axis"]["in_stride"], p["dft_axis"]["out_stride"]
+        axes = p["batch_axes"]
+        dst_name = p["out"]
+        snapshot = src.copy()
+        dst = ws if dst_name == "workspace" else out
+        k = np.arange(N)
+        for idx in itertools.product(*[range(a["size"]) for a in axes]):
+            ib = sum(i * a["in_stride"] for i, a in zip(idx, axes))
+            ob = sum(i * a["out_stride"] for i, a in zip(idx, axes))
+            X = oracle.dft_brute(snapshot[ib + k * ise], sign) if N <= 64 else oracle.fft(snapshot[ib + k * ise], sign)
+            root = p["twiddle_root"]
+            if root:
+                e = (idx[0] * k) % root
+                X = X * np.array([oracle.root(int(ee), root, sign) for ee in e])
+            dst[ob + k * osk] = X
+        src = dst
+    return src
+
+
+@pytest.mark.parametrize("n,batch,lift", [
+    (64, 1, [8, 8]), (256, 2, [16, 16]), (512, 1, [2, 16, 16]), (1024, 3, [4, 8, 32]),
+    (4096, 1, [64, 64]), (2048, 1, [2, 4, 2, 8, 16]), (32, 2, [2, 4, 4]), (128, 1, [128]), (8, 4, None),
+    (4096, 2, [16, 256]),
+])
+def test_lowering_computes_the_dft(n, batch, lift):
+    desc = describe(n, batch, lift)
+    rng = np.random.default_rng(n + batch)
+    x = rng.uniform(-1, 1, n * batch) + 1j * rng.uniform(-1, 1, n * batch)
+    for sign in (-1, 1):
+        got = interpret(desc, x, sign).reshape(batch, n)
+        want = oracle.fft(x.reshape(batch, n), sign)
+        assert np.abs(got - want).max() < 1e-11 * n, (n, batch, lift, sign)
+    for p in desc["passes"]:
+        assert p["threads"] <= 1024 and p["lds_bytes"] <= 160 * 1024
+        assert p["threads"] % 64 == 0 or p["threads"] < 64 or p["blocks"] >= 1
+
+
+def test_two_level_store_is_the_reshape_transpose():
+    # The first pass of a lift <r c> writes frequency k0 of column a'' at
+    # position k0 * r + a'': the paper's reshape-transpose of the <c r> view,
+    # i.e. the transpose of <c r> rho^ x read back as <c r>.
+    r, c = 8, 4
+    d = describe(r * c, 1, [r, c])
+    p0, p1 = d["passes"]
+    assert p0["N"] == c and p0["dft_axis"] == {"in_stride": r, "out_stride": r}
+    assert p0["batch_axes"] == [{"size": r, "in_stride": 1, "out_stride": 1}]
+    assert p0["twiddle_root"] == r * c
+    # last pass: final transpose X[k0 + c k1] <- position k0 * r + a'
+    assert p1["dft_axis"] == {"in_stride": 1, "out_stride": c}
+    assert p1["batch_axes"] == [{"size": c, "in_stride": r, "out_stride": 1}]
+    # index oracle: the final transpose as the reversal of the digit axes
+    D = moa.MArray([c, r], list(range(r * c)))
+    X = moa.transpose(D, [1, 0])
+    for k0 in range(c):
+        for k1 in range(r):
+            # element k0 * r + k1 of D lands at gamma(<k1 k0>; <r c>) = k1 * c + k0
+            assert moa.psi([k1, k0], X) == k0 * r + k1
+
+
+def test_batched_plan_partitions_the_transforms():
+    sizes = [64, 128, 64, 16384, 8, 8192, 8192, 1, 64] * 3
+    h = capi.moa_fft_plan_batched(sizes, flags=HOST)
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    assert d["count"] == len(sizes) and d["elements"] == sum(sizes)
+    groups = d["sizes_by_task_group"]
+    assert [g["n"] for g in groups] == sorted(set(sizes), reverse=True)
+    assert sum(g["tasks"] for g in groups) == d["tasks"]
+    assert d["lds_bytes"] <= 160 * 1024 and d["threads"] == 1024

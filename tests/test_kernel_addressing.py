@@ -1,0 +1,141 @@
+"""CPU check of the pass kernel's launch geometry before it runs on a GPU.
+
+Mirrors, in numpy, the address arithmetic of k_pass (block decode with the
+XCD remap, thread -> (column, row) map, register slots, LDS slots) for every
+block and thread of a plan, and checks that every global load and store
+stays inside the buffer, that every output element is written exactly once,
+and that every LDS slot fits the dynamic LDS the plan requests."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_0803_2386_amd import capi
+
+HOST = capi.MOA_FFT_FLAG_HOST_ONLY
+
+
+def lg_e(lgn):
+    return min(lgn, 4)
+
+
+def pad(i):
+    return i + (i >> 4)
+
+
+def check_pass(p, total, elem_bytes):
+    N = p["N"]
+    lgn = N.bit_length() - 1
+    E = 1 << lg_e(lgn)
+    TPC = N // E
+    W = p["tile_width"]
+    T = p["threads"]
+    assert T == W * TPC and T <= 1024
+    axes = p["batch_axes"]
+    nd = len(axes)
+    blocks = p["blocks"]
+    bid = np.arange(blocks, dtype=np.int64)
+    if p["xcd_remap"]:
+        assert blocks % 8 == 0
+        bid = (bid & 7) * (blocks >> 3) + (bid >> 3)
+        assert np.array_equal(np.sort(bid), np.arange(blocks))
+    if nd == 1:
+        tile, rest = bid, np.zeros_like(bid)
+        assert blocks * W == axes[0]["size"]
+    else:
+        lg_tiles = (axes[0]["size"] // W).bit_length() - 1
+        tile, rest = bid & ((1 << lg_tiles) - 1), bid >> lg_tiles
+    d0 = tile * W
+    ib = d0 * axes[0]["in_stride"]
+    ob = d0 * axes[0]["out_stride"]
+    for d in range(1, nd):
+        if d == nd - 1:
+            idx = rest
+            assert idx.max() < axes[d]["size"]
+        else:
+            lg = axes[d]["size"].bit_length() - 1
+            idx, rest = rest & ((1 << lg) - 1), rest >> lg
+        ib = ib + idx * axes[d]["in_stride"]
+        ob = ob + idx * axes[d]["out_stride"]
+    t = np.arange(T)
+    if p["in_tile_fast"]:
+        w, j = t % W, t // W
+    else:
+        j, w = t % TPC, t // TPC
+    m = np.arange(E)
+    # loads: block x thread x slot
+    rows = j[:, None] + m[None, :] * TPC
+    load = (ib[:, None, None] + (w * axes[0]["in_stride"])[None, :, None]
+            + rows[None, :, :] * p["dft_axis"]["in_stride"])
+    assert load.min() >= 0 and load.max() < total
+    # stores: every (column, k) of every block
+    k = np.arange(N)
+    ww = np.arange(W)
+    store = (ob[:, None, None] + (ww * axes[0]["out_stride"])[None, :, None]
+             + k[None, None, :] * p["dft_axis"]["out_stride"])
+    assert store.min() >= 0 and store.max() < total
+    flat = np.sort(store.ravel())
+    assert flat.size == total and np.array_equal(flat, np.arange(total)), "outputs not a permutation"
+    # LDS slots
+    cs = p["lds_col_stride"]
+    top = (W - 1) * cs + pad(N - 1)
+    assert (top + 1) * elem_bytes <= p["lds_bytes"] <= 160 * 1024
+
+
+@pytest.mark.parametrize("n,batch,lift,dtype", [
+    (1 << 24, 1, [4096, 4096], capi.MOA_C64),
+    (1 << 16, 256, [256, 256], capi.MOA_C64),
+    (1 << 20, 8, [256, 4096], capi.MOA_C64),
+    (1 << 10, 1, None, capi.MOA_C128),
+    (1 << 16, 3, [16, 16, 256], capi.MOA_C64),
+    (2048, 2, [2, 4, 2, 8, 16], capi.MOA_C64),
+    (1, 3, None, capi.MOA_C64), (2, 5, None, capi.MOA_C128), (64, 7, None, capi.MOA_C64),
+    (1 << 14, 2, None, capi.MOA_C64), (1 << 13, 3, None, capi.MOA_C128), (1 << 15, 1, None, capi.MOA_C64),
+    (1 << 18, 1, [64, 4096], capi.MOA_C64), (4096, 1, [256, 16], capi.MOA_C128),
+])
+def test_pass_kernel_geometry(n, batch, lift, dtype):
+    h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST)
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    eb = 8 if dtype == capi.MOA_C64 else 16
+    for p in d["passes"]:
+        check_pass(p, n * batch, eb)
+
+
+@pytest.mark.parametrize("cols", [1, 2, 4, 8, 16, 32, 64])
+def test_tuned_geometry(cols):
+    try:
+        h = capi.moa_fft_plan(1 << 16, 4, [256, 256], flags=HOST, tuning=dict(cols_per_block=[cols, cols]))
+    except capi.MoaError as e:
+        assert e.status == capi.MOA_ERR_TUNING
+        return
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    for p in d["passes"]:
+        check_pass(p, 4 << 16, 8)
+
+
+def test_batched_task_geometry():
+    from paper_0803_2386_amd import inputs
+    sizes = [int(s) for s in inputs.uneven_sizes(8192, 6, 14, seed=0)] + [1, 2, 4, 8, 16, 32]
+    h = capi.moa_fft_plan_batched(sizes, flags=HOST)
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    # every task fits the workgroup and the LDS the launch requests
+    for g in d["sizes_by_task_group"]:
+        N = g["n"]
+        lgn = N.bit_length() - 1
+        TPC = N >> lg_e(lgn)
+        lanes = TPC
+        base = N + (N >> 4)
+        cs = base if lanes >= 16 else base + ((lanes - (base & 31) + 32) & 31)
+        per = min(1024 // TPC, (17408 * 8) // (cs * 8))
+        assert per * TPC <= d["threads"]
+        assert per * cs * 8 <= d["lds_bytes"] <= 160 * 1024
+    assert d["tasks"] == sum(g["tasks"] for g in d["sizes_by_task_group"])
