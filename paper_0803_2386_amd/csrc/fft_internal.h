@@ -67,6 +67,7 @@ struct PassDesc {
     int lds_bytes = 0;
     int xcd_remap = 0;
     int mfma = 0;                 // 0 = VALU radix-16, 1 = split bf16 MFMA, 2 = split fp16 MFMA
+    int pre_lg = 0;               // log2 of the points transformed by earlier levels
 };
 
 // Kernel argument block (passed by value).
@@ -87,6 +88,7 @@ struct PassArgs {
     const void* tw_lo;
     const void* tw_blk;           // omega_{2^14}^e, e < 2^14 (in-block twiddles)
     int xcd_remap;
+    int pre_lg;                   // log2 of the points transformed by earlier levels
     float sign;                   // -1 forward, +1 adjoint
 };
 
@@ -116,6 +118,10 @@ hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d);  // sets LDS attri
 hipError_t launch_batched(bool fp64, const BatchArgs& a, int grid, int threads, int lds_bytes,
                           hipStream_t s);
 hipError_t prepare_batched_kernel(bool fp64, int lds_bytes);
+// Matrix-core levels (fft_mfma.hip): lgn in {4, 8, 12}, d.mfma = 1 (bf16) or 2 (fp16).
+hipError_t launch_mfma(const PassDesc& d, const PassArgs& a, hipStream_t s);
+hipError_t prepare_mfma_kernel(const PassDesc& d);
+const void* mfma_kernel_fn(const PassDesc& d);
 // The kernel function pointers, used to build HIP graph nodes.
 const void* pass_kernel_fn(bool fp64, const PassDesc& d);
 const void* batched_kernel_fn(bool fp64);

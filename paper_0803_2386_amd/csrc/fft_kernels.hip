@@ -160,11 +160,13 @@ static PassFn pass_fn_lookup(bool fp64, int lgn, bool tin, bool tout)
 
 const void* pass_kernel_fn(bool fp64, const PassDesc& d)
 {
+    if (d.mfma) return mfma_kernel_fn(d);
     return reinterpret_cast<const void*>(pass_fn_lookup(fp64, d.lgn, d.in_tile_fast, d.out_tile_fast));
 }
 
 hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d)
 {
+    if (d.mfma) return prepare_mfma_kernel(d);
     PassFn f = pass_fn_lookup(fp64, d.lgn, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -173,6 +175,7 @@ hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d)
 
 hipError_t launch_pass(bool fp64, const PassDesc& d, const PassArgs& a, hipStream_t s)
 {
+    if (d.mfma) return launch_mfma(d, a, s);
     PassFn f = pass_fn_lookup(fp64, d.lgn, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(unsigned(d.blocks)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);

@@ -123,10 +123,13 @@ int64_t add_table(moa_fft_plan_s* p, int64_t L, int64_t count, int64_t step)
 int lgE(int lgn) { return lgn < moa::kLgE ? lgn : moa::kLgE; }
 
 // Fill launch fields of a pass: tile width, mapping, LDS tile, grid.
+// Matrix-core levels use one thread per 16 points like the VALU kernel, and
+// need whole waves: at least 1024 points per workgroup.
 moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w)
 {
     const int lgn = d.lgn;
     const int tpc = 1 << (lgn - lgE(lgn));
+    const int min_lgw = d.mfma ? std::max(0, 10 - lgn) : 0;
     // A lone digit 0 may have any size: its tiles must divide it.
     int lg0 = d.lg[0];
     if (d.nd == 1) {
@@ -147,17 +150,19 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w)
     if (want_w > 0) {
         if (!is_pow2(want_w)) return MOA_ERR_TUNING;
         lgw = lg2(want_w);
-        if (lgw > lg0) return MOA_ERR_TUNING;
+        if (lgw > lg0 || lgw < min_lgw) return MOA_ERR_TUNING;
         if ((int64_t(1) << lgw) * tpc > maxT) return MOA_ERR_TUNING;
         if (lds_for(lgw, in_tf && lgw > 0).second > moa::kLdsBytes) return MOA_ERR_TUNING;
     } else {
         // Default: as many columns as fit 2^14 (c64) / 2^13 (c128) points,
         // the thread limit and LDS, and the digit itself.
         const int target_lg = fp64 ? 13 : 14;
+        lgw = std::min(min_lgw, lg0);
         while (lgw < lg0 && lgn + lgw + 1 <= target_lg && (int64_t(2) << lgw) * tpc <= maxT &&
                lds_for(lgw + 1, in_tf).second <= moa::kLdsBytes)
             ++lgw;
     }
+    if (lgw < min_lgw) return MOA_ERR_LIFT;  // matrix-core level with too few transforms
     d.lgw = lgw;
     d.in_tile_fast = lgw > 0 && in_tf;
     d.out_tile_fast = lgw > 0 && out_tf;
@@ -225,6 +230,9 @@ moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
             for (int i = 0; i < l; ++i) push_digit(d, D[size_t(i)], Rs[size_t(i)], Xs[size_t(i)]);
             if (B > 1 || d.nd == 0) push_digit(d, B, n, n);
         }
+        d.pre_lg = 0;
+        for (int i = 0; i < l; ++i) d.pre_lg += lg2(D[size_t(i)]);
+        if (p->prec != MOA_FFT_PREC_NATIVE && d.lgn % 4 == 0 && d.lgn >= 4 && d.lgn <= 12) d.mfma = p->prec;
         const int want = tuning ? tuning->cols_per_block[l] : 0;
         if (tuning && (want < 0)) return MOA_ERR_TUNING;
         moa_status_t st = finish_pass(d, p->fp64, want);
@@ -353,10 +361,10 @@ std::string describe_json(const moa_fft_plan_s* p)
             add("%s{\"size\":%lld,\"in_stride\":%lld,\"out_stride\":%lld}", i ? "," : "",
                 (long long)d.size[i], (long long)d.in_s[i], (long long)d.out_s[i]);
         add("],\"twiddle_root\":%lld,\"tile_width\":%d,\"threads\":%d,\"blocks\":%lld,\"lds_bytes\":%d,"
-            "\"lds_col_stride\":%d,\"in_tile_fast\":%s,\"out_tile_fast\":%s,\"xcd_remap\":%d}",
+            "\"lds_col_stride\":%d,\"in_tile_fast\":%s,\"out_tile_fast\":%s,\"xcd_remap\":%d,\"mfma\":\"%s\"}",
             d.tw ? (long long)(int64_t(1) << d.tw_lgroot) : 0LL, 1 << d.lgw, d.threads, (long long)d.blocks,
             d.lds_bytes, d.col_stride, d.in_tile_fast ? "true" : "false", d.out_tile_fast ? "true" : "false",
-            d.xcd_remap);
+            d.xcd_remap, d.mfma == 0 ? "none" : (d.mfma == 1 ? "split_bf16" : "split_fp16"));
     }
     s += "]";
     if (p->batched) {
@@ -409,6 +417,7 @@ void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, std:
         a.tw_lo = tb + size_t(d.tw_lo_off) * eb;
         a.tw_blk = tb + size_t(p->tw_blk_off) * eb;
         a.xcd_remap = d.xcd_remap;
+        a.pre_lg = d.pre_lg;
         a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
         args.push_back(a);
     }
@@ -640,7 +649,6 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
             lift.push_back(int64_t(1) << part);
         }
     }
-    if (prec != MOA_FFT_PREC_NATIVE) return MOA_ERR_DTYPE;  // matrix-core path: planned per level below
     moa_fft_plan_s* p = new (std::nothrow) moa_fft_plan_s();
     if (!p) return MOA_ERR_ALLOC;
     p->fp64 = fp64;
