@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run a plain device copy of the same buffer (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -93,6 +95,11 @@ def main():
     value = gflops(n, batch, ms_per_step / 1e3)
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.1f} GFLOP/s",
           file=sys.stderr, flush=True)
+
+    if args.copy_ref:
+        ref = torch.empty_like(x)
+        copy_ms = time_events(lambda: ref.copy_(x), args.steps, torch)
+        print(f"[bench] reference copy of {8 * n} B: {copy_ms:.4f} ms", file=sys.stderr, flush=True)
 
     # Per-level kernel durations (HIP events on the launch stream).
     levels = plan.num_levels

@@ -3,15 +3,15 @@
 // that runs one workgroup-resident transform through VGPRs and LDS.
 //
 // A transform of length N = 2^LGN inside one workgroup is split over
-// TPC = N / E threads that each keep E = 16 elements in registers.  The
-// radix-2 stages of the method (Ch. 3, Fig. rad2_fft, and the hyper-cube
-// butterfly of Ch. 5) are grouped four at a time into register-resident
-// radix-16 blocks; between groups the data crosses LDS once, which is the
-// GPU form of the paper's in-cache reshape: the index bits a thread owns
-// change, the data never leaves the workgroup.  Stages use the self-sorting
-// (Stockham) order, so input and output of every level are in natural order
-// and the bit-reversal permutation P_n of Fig. vanloan_fft is absorbed into
-// the addressing.
+// TPC = N / E threads that each keep E = 2^LGE elements (16 or 32) in
+// registers.  The radix-2 stages of the method (Ch. 3, Fig. rad2_fft, and the
+// hyper-cube butterfly of Ch. 5) are grouped LGE at a time into
+// register-resident radix-2^LGE blocks; between groups the data cross LDS
+// once, which is the GPU form of the paper's in-cache reshape: the index bits
+// a thread owns change, the data never leave the workgroup.  Stages use the
+// self-sorting (Stockham) order, so input and output of every level are in
+// natural order and the bit-reversal permutation P_n of Fig. vanloan_fft is
+// absorbed into the addressing.
 #pragma once
 
 #include "fft_internal.h"
@@ -32,30 +32,36 @@ template <typename V> __device__ __forceinline__ V cmul(V a, V b)
     return mkc(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// cos(2 pi k / 16) for k = 0..4; the rest follow by symmetry.
-__host__ __device__ constexpr double cos16_base(int k)
+// cos(2 pi k / 32) for k = 0..8; the rest follow by symmetry.
+__host__ __device__ constexpr double cos32_base(int k)
 {
     return k == 0 ? 1.0
-         : k == 1 ? 0.92387953251128675612818318939678828682
-         : k == 2 ? 0.70710678118654752440084436210484903928
-         : k == 3 ? 0.38268343236508977172845998403039886676
+         : k == 1 ? 0.98078528040323044912618223613424
+         : k == 2 ? 0.92387953251128675612818318939679
+         : k == 3 ? 0.83146961230254523707878837761791
+         : k == 4 ? 0.70710678118654752440084436210485
+         : k == 5 ? 0.55557023301960222474283081394853
+         : k == 6 ? 0.38268343236508977172845998403040
+         : k == 7 ? 0.19509032201612826784828486847702
                   : 0.0;
 }
-__host__ __device__ constexpr double cos16(int k)
+__host__ __device__ constexpr double cos32(int k)
 {
-    k &= 15;
-    return k <= 4 ? cos16_base(k) : k <= 8 ? -cos16_base(8 - k) : k <= 12 ? -cos16_base(k - 8) : cos16_base(16 - k);
+    k &= 31;
+    return k <= 8 ? cos32_base(k) : k <= 16 ? -cos32_base(16 - k) : k <= 24 ? -cos32_base(k - 16) : cos32_base(32 - k);
 }
-__host__ __device__ constexpr double sin16(int k) { return cos16((k + 12) & 15); }
+__host__ __device__ constexpr double sin32(int k) { return cos32((k + 24) & 31); }
+__host__ __device__ constexpr double cos16(int k) { return cos32(2 * k); }
+__host__ __device__ constexpr double sin16(int k) { return sin32(2 * k); }
 
-// d * omega_16^K with omega = exp(sign * 2 pi i / 16); K is a constant after
+// d * omega_32^K with omega = exp(sign * 2 pi i / 32); K is a constant after
 // unrolling, so the trivial factors 1 and -+i cost no multiplies.
 template <typename R, typename V>
-__device__ __forceinline__ V rot16(V d, int K, R sign)
+__device__ __forceinline__ V rot32(V d, int K, R sign)
 {
     if (K == 0) return d;
-    if (K == 4) return mkc(-sign * d.y, sign * d.x);
-    const R c = (R)cos16(K), s = sign * (R)sin16(K);
+    if (K == 8) return mkc(-sign * d.y, sign * d.x);
+    const R c = (R)cos32(K), s = sign * (R)sin32(K);
     return mkc(d.x * c - d.y * s, d.x * s + d.y * c);
 }
 
@@ -67,12 +73,13 @@ __host__ __device__ constexpr int bitrev_small(int k, int lg)
     return r;
 }
 
-// In-register DFT of length 2^LGR (<= 16) on v[0..RS): radix-2 stages by
+// In-register DFT of length 2^LGR (<= 32) on v[0..RS): radix-2 stages by
 // decimation in frequency, then the bit-reversal folded into register names.
 template <typename R, int LGR, typename V>
 __device__ __forceinline__ void dft_reg(V* v, R sign)
 {
     constexpr int RS = 1 << LGR;
+    static_assert(RS <= 32, "register DFT up to 32 points");
     if constexpr (RS > 1) {
 #pragma unroll
         for (int h = RS / 2; h >= 1; h >>= 1) {
@@ -82,7 +89,7 @@ __device__ __forceinline__ void dft_reg(V* v, R sign)
                 for (int i = 0; i < h; ++i) {
                     V a = v[blk + i], b = v[blk + i + h];
                     v[blk + i] = cadd(a, b);
-                    v[blk + i + h] = rot16<R>(csub(a, b), i * (8 / h), sign);
+                    v[blk + i + h] = rot32<R>(csub(a, b), i * (16 / h), sign);
                 }
             }
         }
@@ -94,16 +101,18 @@ __device__ __forceinline__ void dft_reg(V* v, R sign)
     }
 }
 
-// Stage schedule of a length-2^lgn transform: radix-16 stages, then one
-// stage with the remaining radix.
-__host__ __device__ constexpr int lg_e(int lgn) { return lgn < kLgE ? lgn : kLgE; }
+// Stage schedule of a length-2^lgn transform: radix-16 stages, then one stage
+// with the remaining radix.  A thread holds 2^lge points (16 or 32), i.e.
+// NB = 2^lge / radix butterflies of each stage.
+constexpr int kLgRadix = 4;
+__host__ __device__ constexpr int lg_e(int lgn, int lge) { return lgn < lge ? lgn : lge; }
 __host__ __device__ constexpr int n_stages(int lgn)
 {
-    return lgn <= kLgE ? 1 : lgn / kLgE + ((lgn % kLgE) ? 1 : 0);
+    return lgn <= kLgRadix ? 1 : lgn / kLgRadix + ((lgn % kLgRadix) ? 1 : 0);
 }
 __host__ __device__ constexpr int stage_lgr(int lgn, int s)
 {
-    return lgn <= kLgE ? lgn : (s < lgn / kLgE ? kLgE : lgn % kLgE);
+    return lgn <= kLgRadix ? lgn : (s < lgn / kLgRadix ? kLgRadix : lgn % kLgRadix);
 }
 __host__ __device__ constexpr int stage_lgns(int lgn, int s)
 {
@@ -112,36 +121,94 @@ __host__ __device__ constexpr int stage_lgns(int lgn, int s)
     return acc;
 }
 
-// Workgroup size limit per element type: complex128 blocks are at most 2^13
-// points, i.e. 512 threads of 16 elements, which leaves 256 VGPRs a lane.
-template <typename R>
-__host__ __device__ constexpr int max_threads_for() { return sizeof(R) == 8 ? 512 : kMaxThreads; }
-
-// Root of the in-block twiddle table: omega_{2^14}^e for e < 2^14.
+// Root of the in-block twiddle table: omega_{2^14}^e for e < 2^14.  Kernels
+// keep it in LDS as two 128-entry halves, lo[e] = omega^e and
+// hi[e] = omega^(128 e), so omega^e = lo[e mod 128] * hi[e / 128] (one extra
+// rounding); reading twiddles from LDS keeps the in-order vector-memory
+// counter free for the data loads of the next tile.
 constexpr int kLgTwBlk = 14;
+
+template <typename V>
+__device__ __forceinline__ V tw_blk(const V* tl, int e)
+{
+    return cmul(tl[e & 127], tl[128 + (e >> 7)]);
+}
+
+// Inter-level twiddle omega_{2^R}^e from `parts` 256-entry LDS tables,
+// part p holding omega^(e_p 2^(8p)) for the p-th byte e_p of e.
+template <typename V>
+__device__ __forceinline__ V tw_inter(const V* tt, int parts, uint64_t e)
+{
+    V w = tt[e & 255];
+    for (int p = 1; p < parts; ++p) w = cmul(w, tt[256 * p + ((e >> (8 * p)) & 255)]);
+    return w;
+}
+
+template <int LGN, int LGE, int S>
+struct StageTw {
+    static constexpr int N = 1 << LGN;
+    static constexpr int LGR = stage_lgr(LGN, S);
+    static constexpr int RS = 1 << LGR;
+    static constexpr int LGNS = stage_lgns(LGN, S);
+    static constexpr int NS = 1 << LGNS;
+    static constexpr int E = 1 << lg_e(LGN, LGE);
+    static constexpr int TPC = N / E;
+    static constexpr int NB = E / RS;
+};
+
+// Register slot of the point j + m*TPC a thread loads before stage 0: input r
+// of butterfly q sits in slot q*RS + r and is point j + (q + r*NB)*TPC.
+template <int LGN, int LGE>
+__host__ __device__ constexpr int in_slot(int m)
+{
+    using I = StageTw<LGN, LGE, 0>;
+    return (m % I::NB) * I::RS + m / I::NB;
+}
+
+// Twiddles of stage S: input r of the thread's butterfly q is multiplied by
+// omega_{NS*RS}^(bm*r), bm = butterfly index mod NS.  Only the powers
+// r = 2^b are read from the table, tw[q * LGR + b]; input r is multiplied by
+// the powers of its set bits in turn (at most five roundings).
+constexpr int kMaxStageTw = 16;
+
+template <typename R, int LGN, int LGE, int S, typename V>
+__device__ __forceinline__ void load_stage_twiddles(V (&tw)[kMaxStageTw], int j, R sign, const V* tl)
+{
+    using I = StageTw<LGN, LGE, S>;
+    if constexpr (S < n_stages(LGN) && I::NS > 1) {
+        static_assert(I::NB * I::LGR <= kMaxStageTw, "stage twiddle buffer too small");
+#pragma unroll
+        for (int q = 0; q < I::NB; ++q) {
+            const int bm = (j + q * I::TPC) & (I::NS - 1);
+            const int e1 = bm << (kLgTwBlk - I::LGNS - I::LGR);
+#pragma unroll
+            for (int b = 0; b < I::LGR; ++b) {
+                V w = tw_blk(tl, e1 << b);
+                w.y = -sign * w.y;  // the table holds forward roots
+                tw[q * I::LGR + b] = w;
+            }
+        }
+    }
+}
 
 // Run stages S.. of a length-2^LGN transform held by this thread.
 // Register v[q*RS + r] is input r of the thread's q-th butterfly of the
-// stage.  On entry to stage 0, v[m] holds element j + m*TPC (loaded from
-// global memory) unless FROM_LDS, in which case the stage reads it from
+// stage.  On entry to stage 0, v[in_slot(m)] holds element j + m*TPC (loaded
+// from global memory) unless FROM_LDS, in which case the stage reads it from
 // `col` like every later stage.  Every stage but the last leaves its output
 // in `col` (padded, natural Stockham positions); the last leaves it in v,
-// with v[q*RS + r] = output element j + (q + r*NB)*TPC, NB = E/RS.
-// Threads with active == false only take part in the barriers.
-template <typename R, int LGN, int S, bool FROM_LDS, typename V>
-__device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V* __restrict__ twb,
-                                           bool active)
+// with v[q*RS + r] = output element j + (q + r*NB)*TPC, NB = E/RS.  `tw`
+// holds the stage's twiddle powers, read one stage ahead from the LDS table
+// `twb` (see tw_blk).  Threads with active == false only take part in the
+// barriers.
+template <typename R, int LGN, int LGE, int S, bool FROM_LDS, typename V>
+__device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V* twb, bool active,
+                                           V (&tw)[kMaxStageTw])
 {
     constexpr int NST = n_stages(LGN);
     if constexpr (S < NST) {
-        constexpr int N = 1 << LGN;
-        constexpr int LGR = stage_lgr(LGN, S);
-        constexpr int RS = 1 << LGR;
-        constexpr int LGNS = stage_lgns(LGN, S);
-        constexpr int NS = 1 << LGNS;
-        constexpr int E = 1 << lg_e(LGN);
-        constexpr int TPC = N / E;
-        constexpr int NB = E / RS;
+        using I = StageTw<LGN, LGE, S>;
+        constexpr int N = I::N, LGR = I::LGR, RS = I::RS, LGNS = I::LGNS, NS = I::NS, TPC = I::TPC, NB = I::NB;
         constexpr bool READS_LDS = (S > 0) || FROM_LDS;
         if constexpr (READS_LDS) {
             if (active) {
@@ -155,20 +222,20 @@ __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V*
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 if constexpr (NS > 1) {
-                    const int bm = (j + q * TPC) & (NS - 1);
 #pragma unroll
                     for (int r = 1; r < RS; ++r) {
-                        // omega_{NS*RS}^(bm*r) = omega_{2^14}^(bm*r*2^(14-LGNS-LGR))
-                        const int e = (bm * r) << (kLgTwBlk - LGNS - LGR);
-                        V w = twb[e];
-                        w.y = -sign * w.y;  // table holds forward roots
-                        v[q * RS + r] = cmul(v[q * RS + r], w);
+                        V x = v[q * RS + r];
+#pragma unroll
+                        for (int b = 0; b < LGR; ++b)
+                            if (r & (1 << b)) x = cmul(x, tw[q * LGR + b]);
+                        v[q * RS + r] = x;
                     }
                 }
                 dft_reg<R, LGR>(v + q * RS, sign);
             }
         }
         if constexpr (S + 1 < NST) {
+            if (active) load_stage_twiddles<R, LGN, LGE, S + 1>(tw, j, sign, twb);
             if constexpr (READS_LDS) __syncthreads();
             if (active) {
 #pragma unroll
@@ -180,23 +247,18 @@ __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V*
                 }
             }
             __syncthreads();
-            run_stages<R, LGN, S + 1, FROM_LDS>(v, col, j, sign, twb, active);
+            run_stages<R, LGN, LGE, S + 1, FROM_LDS>(v, col, j, sign, twb, active, tw);
         }
     }
 }
 
-// Output element held in register slot m after the last stage.
-template <int LGN>
-__device__ __forceinline__ constexpr int out_index_of_slot(int m, int j)
+// Position, in units of TPC past the thread's row j, of the output element
+// held in register slot m after the last stage.
+template <int LGN, int LGE>
+__host__ __device__ constexpr int out_slot_rank(int m)
 {
-    constexpr int LAST = n_stages(LGN) - 1;
-    constexpr int LGR = stage_lgr(LGN, LAST);
-    constexpr int RS = 1 << LGR;
-    constexpr int E = 1 << lg_e(LGN);
-    constexpr int NB = E / RS;
-    constexpr int TPC = (1 << LGN) / E;
-    const int q = m / RS, r = m % RS;
-    return j + (q + r * NB) * TPC;
+    using I = StageTw<LGN, LGE, n_stages(LGN) - 1>;
+    return m / I::RS + (m % I::RS) * I::NB;
 }
 
 }  // namespace moa

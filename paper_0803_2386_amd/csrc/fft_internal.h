@@ -8,14 +8,20 @@
 namespace moa {
 
 constexpr int kMaxDigits = 8;     // batch digits of one pass descriptor
-constexpr int kMaxThreads = 1024; // workgroup size limit of every kernel
+constexpr int kMaxThreads = 512;  // workgroup size limit (1024 for the large staged-store level kernel)
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kMaxLgBlockC64 = 14;  // 2^14 complex64 = 128 KiB (+pad) in LDS
 constexpr int kMaxLgBlockC128 = 13; // 2^13 complex128
 
+// Entries of the in-block twiddle table kept in LDS (two halves of 128).
+constexpr int kTwBlkEntries = 256;
+// Most transforms one task of the uneven batch holds (one per thread).
+constexpr int kMaxTaskCols = 512;
+
 // Elements each thread keeps in registers across a pass (the radix of the
-// register-resident stages).  Transforms shorter than this use one thread.
-constexpr int kLgE = 4;
+// register-resident stages) is 2^lge, lge = 4 or 5; a transform shorter than
+// that uses one thread.
+constexpr int kLgE = 4;  // the default; tiles that would need more than 512 threads use 5
 
 // Element index -> padded LDS slot: one spare slot after every 16 elements
 // breaks the power-of-two strides of the butterfly exchanges across banks.
@@ -53,17 +59,21 @@ struct PassDesc {
     int64_t in_s[kMaxDigits] = {0};
     int64_t out_s[kMaxDigits] = {0};
     int lgw = 0;                  // log2 transforms per workgroup (tile width)
+    int lge = kLgE;               // log2 points per thread
+    int kmode = 0;                // level kernel variant (see fft_kernels.hip)
     // Inter-level twiddle omega_{2^tw_lgroot}^(d0 * k), d0 = value of digit 0.
     int tw = 0;
     int tw_lgroot = 0;
-    int tw_lglo = 0;              // split of the two-level twiddle table
-    int64_t tw_hi_off = 0, tw_lo_off = 0;  // offsets (elements) into the plan's table buffer
+    int tw_parts = 0;             // byte-wise parts of the exponent (256-entry tables each)
+    int64_t tw_inter_off = 0;     // offset (elements) of the part tables in the plan's table buffer
     // Launch shape (filled by the planner).
     bool in_tile_fast = false;    // digit 0 is the unit-stride input axis
     bool out_tile_fast = false;   // digit 0 is the unit-stride output axis
     int threads = 0;
     int col_stride = 0;           // LDS column stride in elements
-    int64_t blocks = 0;
+    int64_t blocks = 0;           // tiles (logical workgroups)
+    int64_t grid = 0;             // resident workgroups of the persistent launch
+    int data_elems = 0;           // LDS elements of the data tile (tables follow)
     int lds_bytes = 0;
     int xcd_remap = 0;
     int mfma = 0;                 // 0 = VALU radix-16, 1 = split bf16 MFMA, 2 = split fp16 MFMA
@@ -82,11 +92,12 @@ struct PassArgs {
     int lgw;
     int lg_tiles;                 // log2(size of digit 0 / tile width)
     int col_stride;
-    int tw;
-    int tw_lgroot, tw_lglo;
-    const void* tw_hi;
-    const void* tw_lo;
-    const void* tw_blk;           // omega_{2^14}^e, e < 2^14 (in-block twiddles)
+    int tw_parts;                 // 0: no inter-level twiddle
+    int tw_lgroot;
+    const void* tw_inter;         // tw_parts x 256 entries, part p = omega^(e 2^(8p))
+    const void* tw_blk;           // 2 x 128 entries: omega_{2^14}^e and omega_{2^14}^(128 e)
+    int64_t ntiles;               // tiles of the launch
+    int data_elems;               // LDS elements of the data tile
     int xcd_remap;
     int pre_lg;                   // log2 of the points transformed by earlier levels
     float sign;                   // -1 forward, +1 adjoint
@@ -108,6 +119,7 @@ struct BatchArgs {
     const void* tw_blk;
     int ntasks;
     int task0;                    // first task of this launch
+    int data_elems;               // LDS elements of the data tile (tables follow)
     float sign;
 };
 

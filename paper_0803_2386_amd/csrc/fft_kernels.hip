@@ -18,62 +18,33 @@
 // digit) is the unit-stride axis of the input (TIN) or output (TOUT).  The
 // thread <-> (column, row) map is chosen so that the global loads coalesce;
 // if the store wants the other map, the tile goes back through LDS first.
+//
+// The grid is persistent: each workgroup walks a run of tiles and issues the
+// loads of its next tile before it transforms the current one, so the HBM
+// transfer of one tile overlaps the LDS/VALU work of the previous one.  All
+// twiddles come from small LDS tables, leaving the in-order vector-memory
+// counter to the data loads.  On each XCD the resident workgroups take
+// consecutive tiles, so tiles that share cache lines meet in the same L2.
 #include "fft_device.h"
 
 namespace moa {
 
-template <typename R, typename V>
-__device__ __forceinline__ V inter_level_twiddle(const PassArgs& a, int64_t d0, int k, R sign)
+// Element offsets of tile `tile`: its first value of digit 0 and the input and
+// output offsets of the remaining digits.
+__device__ __forceinline__ void tile_offsets(const PassArgs& a, uint64_t tile_id, int64_t& d0, int64_t& ib,
+                                             int64_t& ob)
 {
-    const uint64_t mask = (uint64_t(1) << a.tw_lgroot) - 1;
-    const uint64_t e = (uint64_t(d0) * uint64_t(k)) & mask;
-    const V* hi = reinterpret_cast<const V*>(a.tw_hi);
-    const V* lo = reinterpret_cast<const V*>(a.tw_lo);
-    V w = cmul(hi[e >> a.tw_lglo], lo[e & ((uint64_t(1) << a.tw_lglo) - 1)]);
-    w.y = -sign * w.y;
-    return w;
-}
-
-template <typename R, int LGN, bool TIN, bool TOUT>
-__global__ void __launch_bounds__(max_threads_for<R>()) k_pass(PassArgs a)
-{
-    using V = typename cpx<R>::V;
-    constexpr int LGE = lg_e(LGN);
-    constexpr int E = 1 << LGE;
-    constexpr int LGTPC = LGN - LGE;
-    constexpr int TPC = 1 << LGTPC;
-
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    V* lds = reinterpret_cast<V*>(smem_raw);
-    const R sign = (R)a.sign;
-    const int lgw = a.lgw;
-    const int t = threadIdx.x;
-    int w, j;
-    if constexpr (TIN) {
-        w = t & ((1 << lgw) - 1);
-        j = t >> lgw;
-    } else {
-        j = t & (TPC - 1);
-        w = t >> LGTPC;
-    }
-
-    // Logical block: the dispatcher deals blocks round-robin over the 8 XCDs;
-    // remapping gives each XCD a contiguous range of tiles, so tiles that
-    // share cache lines meet in the same L2.
-    uint32_t bid = blockIdx.x;
-    if (a.xcd_remap) bid = (bid & 7u) * (gridDim.x >> 3) + (bid >> 3);
-    // Digit 0 holds the tile (alone, it may have any size); the last digit
-    // takes the rest of the block index; the ones between are powers of two.
     uint64_t tile, rest;
     if (a.nd == 1) {
-        tile = bid;
+        tile = tile_id;
         rest = 0;
     } else {
-        tile = bid & ((uint64_t(1) << a.lg_tiles) - 1);
-        rest = uint64_t(bid) >> a.lg_tiles;
+        tile = tile_id & ((uint64_t(1) << a.lg_tiles) - 1);
+        rest = tile_id >> a.lg_tiles;
     }
-    const int64_t d0 = int64_t(tile << lgw);
-    int64_t ib = d0 * a.in_s[0], ob = d0 * a.out_s[0];
+    d0 = int64_t(tile << a.lgw);
+    ib = d0 * a.in_s[0];
+    ob = d0 * a.out_s[0];
     for (int d = 1; d < a.nd; ++d) {
         int64_t idx;
         if (d + 1 == a.nd) {
@@ -85,89 +56,223 @@ __global__ void __launch_bounds__(max_threads_for<R>()) k_pass(PassArgs a)
         ib += idx * a.in_s[d];
         ob += idx * a.out_s[d];
     }
+}
 
-    V v[E];
-    {
-        const V* __restrict__ src = reinterpret_cast<const V*>(a.in) + ib + int64_t(w) * a.in_s[0];
+// Load the points of tile `tile_id` this thread owns (slot order of stage 0).
+template <int LGN, int LGE, typename V>
+__device__ __forceinline__ void prefetch_now(const PassArgs& a, uint64_t tile_id, int64_t& d0, int64_t& ib,
+                                             int64_t& ob, const V* gin, int w, int j, V* vn)
+{
+    constexpr int LE = lg_e(LGN, LGE);
+    constexpr int TPC = 1 << (LGN - LE);
+    tile_offsets(a, tile_id, d0, ib, ob);
+    const V* src = gin + ib + int64_t(w) * a.in_s[0];
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = src[int64_t(j + m * TPC) * a.in_s_e];
-    }
-    const V* __restrict__ twb = reinterpret_cast<const V*>(a.tw_blk);
-    V* col = lds + w * a.col_stride;
-    run_stages<R, LGN, 0, false>(v, col, j, sign, twb, true);
+    for (int m = 0; m < (1 << LE); ++m) vn[in_slot<LGN, LGE>(m)] = src[int64_t(j + m * TPC) * a.in_s_e];
+}
 
-    if constexpr (TIN == TOUT) {
-        V* __restrict__ dst = reinterpret_cast<V*>(a.out) + ob + int64_t(w) * a.out_s[0];
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int k = out_index_of_slot<LGN>(m, j);
-            V y = v[m];
-            if (a.tw) y = cmul(y, inter_level_twiddle<R, V>(a, d0 + w, k, sign));
-            dst[int64_t(k) * a.out_s_k] = y;
-        }
+// Kernel modes: 0 = 16 points a thread, <= 512 threads, next tile prefetched;
+// 1 = 32 points a thread, <= 512 threads, prefetched (levels that store in
+// their load pattern); 2 = 16 points a thread, <= 1024 threads, no prefetch
+// (large tiles whose store goes through LDS: two tiles do not fit the VGPRs).
+__host__ __device__ constexpr int mode_lge(int km) { return km == 1 ? 5 : 4; }
+__host__ __device__ constexpr int mode_threads(int km) { return km == 2 ? 1024 : 512; }
+
+template <typename R, int LGN, int KM, bool TIN, bool TOUT>
+__global__ void __launch_bounds__(mode_threads(KM)) k_pass(PassArgs a)
+{
+    using V = typename cpx<R>::V;
+    constexpr int LGE = mode_lge(KM);
+    constexpr int LE = lg_e(LGN, LGE);
+    constexpr int E = 1 << LE;
+    constexpr int LGTPC = LGN - LE;
+    constexpr int TPC = 1 << LGTPC;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    V* tl = lds + a.data_elems;          // in-block twiddles (256)
+    V* tt = tl + kTwBlkEntries;          // inter-level twiddles (256 per part)
+    const R sign = (R)a.sign;
+    const int lgw = a.lgw;
+    const int t = threadIdx.x, T = blockDim.x;
+    int w, j;
+    if constexpr (TIN) {
+        w = t & ((1 << lgw) - 1);
+        j = t >> lgw;
     } else {
-        if constexpr (n_stages(LGN) > 1) __syncthreads();
+        j = t & (TPC - 1);
+        w = t >> LGTPC;
+    }
+
+    {
+        const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
+        for (int i = t; i < kTwBlkEntries; i += T) tl[i] = g1[i];
+        const V* g2 = reinterpret_cast<const V*>(a.tw_inter);
+        for (int i = t; i < 256 * a.tw_parts; i += T) tt[i] = g2[i];
+    }
+    __syncthreads();
+
+    // Tile run of this workgroup.
+    uint64_t tile, end, step;
+    if (a.xcd_remap) {
+        const uint64_t per_xcd = gridDim.x >> 3;
+        const uint64_t chunk = (uint64_t(a.ntiles) + 7) >> 3;
+        const uint64_t x = blockIdx.x & 7u;
+        tile = x * chunk + (blockIdx.x >> 3);
+        end = min(uint64_t(a.ntiles), (x + 1) * chunk);
+        step = per_xcd;
+    } else {
+        tile = blockIdx.x;
+        end = uint64_t(a.ntiles);
+        step = gridDim.x;
+    }
+
+    const V* __restrict__ gin = reinterpret_cast<const V*>(a.in);
+    V* __restrict__ gout = reinterpret_cast<V*>(a.out);
+    V v[E];
+    int64_t d0 = 0, ib = 0, ob = 0;
+    if (tile < end) {
+        tile_offsets(a, tile, d0, ib, ob);
+        const V* src = gin + ib + int64_t(w) * a.in_s[0];
 #pragma unroll
-        for (int m = 0; m < E; ++m) col[lds_pad(out_index_of_slot<LGN>(m, j))] = v[m];
-        __syncthreads();
-        int w2, j2;
-        if constexpr (TOUT) {
-            w2 = t & ((1 << lgw) - 1);
-            j2 = t >> lgw;
-        } else {
-            j2 = t & (TPC - 1);
-            w2 = t >> LGTPC;
-        }
-        const V* col2 = lds + w2 * a.col_stride;
-        V* __restrict__ dst = reinterpret_cast<V*>(a.out) + ob + int64_t(w2) * a.out_s[0];
+        for (int m = 0; m < E; ++m) v[in_slot<LGN, LGE>(m)] = src[int64_t(j + m * TPC) * a.in_s_e];
+    }
+    // Mode 2 runs one tile per workgroup (grid = tiles): without a prefetch a
+    // tile loop buys nothing and costs registers.
+    constexpr bool kPersistent = KM != 2;
+    for (int once = 0; kPersistent ? (tile < end) : (once == 0 && tile < end); ++once) {
+        // Hide the thread coordinates from loop-invariant code motion: every
+        // LDS address of the stages derives from them, and hoisting those
+        // out of the tile loop would keep hundreds of addresses live.
+        asm volatile("" : "+v"(j), "+v"(w));
+        V* col = lds + w * a.col_stride;
+        const uint64_t next = tile + step;
+        int64_t nd0 = 0, nib = 0, nob = 0;
+        V vn[E];
+        // Prefetch the next tile of the run into registers: before the stages
+        // when the store needs no LDS pass, else once the stage outputs have
+        // left the registers for LDS (so both tiles never sit in VGPRs while
+        // the stages run).
+        // complex128 plans are for accuracy, not bandwidth: no prefetch there.
+        constexpr bool kPrefetch = sizeof(R) == 4 && KM != 2;
+        auto prefetch = [&]() {
+            if (kPrefetch && next < end) prefetch_now<LGN, LGE>(a, next, nd0, nib, nob, gin, w, j, vn);
+        };
+        if constexpr (TIN == TOUT) prefetch();
+
+        V tw[kMaxStageTw];
+        run_stages<R, LGN, LGE, 0, false>(v, col, j, sign, tl, true, tw);
+
+        // Store phase.  rank(m): the output row of slot m is jst + rank * TPC.
+        int wst = w, jst = j;
+        if constexpr (TIN != TOUT) {
+            if constexpr (n_stages(LGN) > 1) __syncthreads();
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int k = j2 + m * TPC;
-            V y = col2[lds_pad(k)];
-            if (a.tw) y = cmul(y, inter_level_twiddle<R, V>(a, d0 + w2, k, sign));
-            dst[int64_t(k) * a.out_s_k] = y;
+            for (int m = 0; m < E; ++m) col[lds_pad(j + out_slot_rank<LGN, LGE>(m) * TPC)] = v[m];
+            prefetch();
+            __syncthreads();
+            if constexpr (TOUT) {
+                wst = t & ((1 << lgw) - 1);
+                jst = t >> lgw;
+            } else {
+                jst = t & (TPC - 1);
+                wst = t >> LGTPC;
+            }
+            const V* col2 = lds + wst * a.col_stride;
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = col2[lds_pad(jst + m * TPC)];
         }
+        auto rank = [&](int m) {
+            if constexpr (TIN == TOUT) return out_slot_rank<LGN, LGE>(m);
+            else return m;
+        };
+        // The inter-level factor only occurs on levels that store in their
+        // load pattern (every level but the last); the planner guarantees it.
+        if (TIN == TOUT && a.tw_parts) {
+            // omega^(dcol * (jst + rank * TPC)) = base * prod over the set bits
+            // b of rank of omega^(dcol * TPC * 2^b).
+            const uint64_t mask = (uint64_t(1) << a.tw_lgroot) - 1;
+            const uint64_t dcol = uint64_t(d0 + wst);
+            V base = tw_inter(tt, a.tw_parts, (dcol * uint64_t(jst)) & mask);
+            base.y = -sign * base.y;
+            V pw[LE > 0 ? LE : 1];
+#pragma unroll
+            for (int b = 0; b < LE; ++b) {
+                pw[b] = tw_inter(tt, a.tw_parts, (dcol * (uint64_t(TPC) << b)) & mask);
+                pw[b].y = -sign * pw[b].y;
+            }
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                V f = base;
+#pragma unroll
+                for (int b = 0; b < LE; ++b)
+                    if (rank(m) & (1 << b)) f = cmul(f, pw[b]);
+                v[m] = cmul(v[m], f);
+            }
+        }
+        V* dst = gout + ob + int64_t(wst) * a.out_s[0];
+#pragma unroll
+        for (int m = 0; m < E; ++m) dst[int64_t(jst + rank(m) * TPC) * a.out_s_k] = v[m];
+
+        if constexpr (!kPersistent) break;
+        __syncthreads();  // the next tile overwrites the LDS exchange buffer
+        if (!kPrefetch && next < end) prefetch_now<LGN, LGE>(a, next, nd0, nib, nob, gin, w, j, vn);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = vn[m];
+        tile = next;
+        d0 = nd0;
+        ib = nib;
+        ob = nob;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Kernel table: [fp64][lgn][tin][tout]
+// Kernel table: [lgn][mode][tin][tout]; mode 1 exists for tin == tout only,
+// mode 2 for tin != tout only, complex128 uses mode 0.
 // ---------------------------------------------------------------------------
 using PassFn = void (*)(PassArgs);
 
-#define MOA_PASS_ROW(R, L) \
-    { &k_pass<R, L, false, false>, &k_pass<R, L, false, true>, &k_pass<R, L, true, false>, &k_pass<R, L, true, true> }
+#define MOA_PASS_ROW32(L)                                                                                      \
+    {                                                                                                          \
+        {&k_pass<float, L, 0, false, false>, &k_pass<float, L, 0, false, true>, &k_pass<float, L, 0, true, false>, \
+         &k_pass<float, L, 0, true, true>},                                                                    \
+            {&k_pass<float, L, 1, false, false>, nullptr, nullptr, &k_pass<float, L, 1, true, true>},          \
+        {                                                                                                      \
+            nullptr, &k_pass<float, L, 2, false, true>, &k_pass<float, L, 2, true, false>, nullptr             \
+        }                                                                                                      \
+    }
+#define MOA_PASS_MODES64(L) \
+    { &k_pass<double, L, 0, false, false>, &k_pass<double, L, 0, false, true>, &k_pass<double, L, 0, true, false>, \
+      &k_pass<double, L, 0, true, true> }
 
-static const PassFn kPass32[kMaxLgBlockC64 + 1][4] = {
-    MOA_PASS_ROW(float, 0),  MOA_PASS_ROW(float, 1),  MOA_PASS_ROW(float, 2),  MOA_PASS_ROW(float, 3),
-    MOA_PASS_ROW(float, 4),  MOA_PASS_ROW(float, 5),  MOA_PASS_ROW(float, 6),  MOA_PASS_ROW(float, 7),
-    MOA_PASS_ROW(float, 8),  MOA_PASS_ROW(float, 9),  MOA_PASS_ROW(float, 10), MOA_PASS_ROW(float, 11),
-    MOA_PASS_ROW(float, 12), MOA_PASS_ROW(float, 13), MOA_PASS_ROW(float, 14)};
+static const PassFn kPass32[kMaxLgBlockC64 + 1][3][4] = {
+    MOA_PASS_ROW32(0),  MOA_PASS_ROW32(1),  MOA_PASS_ROW32(2),  MOA_PASS_ROW32(3),  MOA_PASS_ROW32(4),
+    MOA_PASS_ROW32(5),  MOA_PASS_ROW32(6),  MOA_PASS_ROW32(7),  MOA_PASS_ROW32(8),  MOA_PASS_ROW32(9),
+    MOA_PASS_ROW32(10), MOA_PASS_ROW32(11), MOA_PASS_ROW32(12), MOA_PASS_ROW32(13), MOA_PASS_ROW32(14)};
 
 static const PassFn kPass64[kMaxLgBlockC128 + 1][4] = {
-    MOA_PASS_ROW(double, 0),  MOA_PASS_ROW(double, 1),  MOA_PASS_ROW(double, 2),  MOA_PASS_ROW(double, 3),
-    MOA_PASS_ROW(double, 4),  MOA_PASS_ROW(double, 5),  MOA_PASS_ROW(double, 6),  MOA_PASS_ROW(double, 7),
-    MOA_PASS_ROW(double, 8),  MOA_PASS_ROW(double, 9),  MOA_PASS_ROW(double, 10), MOA_PASS_ROW(double, 11),
-    MOA_PASS_ROW(double, 12), MOA_PASS_ROW(double, 13)};
+    MOA_PASS_MODES64(0),  MOA_PASS_MODES64(1),  MOA_PASS_MODES64(2),  MOA_PASS_MODES64(3),  MOA_PASS_MODES64(4),
+    MOA_PASS_MODES64(5),  MOA_PASS_MODES64(6),  MOA_PASS_MODES64(7),  MOA_PASS_MODES64(8),  MOA_PASS_MODES64(9),
+    MOA_PASS_MODES64(10), MOA_PASS_MODES64(11), MOA_PASS_MODES64(12), MOA_PASS_MODES64(13)};
 
-static PassFn pass_fn_lookup(bool fp64, int lgn, bool tin, bool tout)
+static PassFn pass_fn_lookup(bool fp64, int lgn, int km, bool tin, bool tout)
 {
     const int mode = (tin ? 2 : 0) + (tout ? 1 : 0);
-    if (lgn < 0) return nullptr;
-    if (fp64) return lgn <= kMaxLgBlockC128 ? kPass64[lgn][mode] : nullptr;
-    return lgn <= kMaxLgBlockC64 ? kPass32[lgn][mode] : nullptr;
+    if (lgn < 0 || km < 0 || km > 2) return nullptr;
+    if (fp64) return (lgn <= kMaxLgBlockC128 && km == 0) ? kPass64[lgn][mode] : nullptr;
+    return lgn <= kMaxLgBlockC64 ? kPass32[lgn][km][mode] : nullptr;
 }
 
 const void* pass_kernel_fn(bool fp64, const PassDesc& d)
 {
     if (d.mfma) return mfma_kernel_fn(d);
-    return reinterpret_cast<const void*>(pass_fn_lookup(fp64, d.lgn, d.in_tile_fast, d.out_tile_fast));
+    return reinterpret_cast<const void*>(pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast));
 }
 
 hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d)
 {
     if (d.mfma) return prepare_mfma_kernel(d);
-    PassFn f = pass_fn_lookup(fp64, d.lgn, d.in_tile_fast, d.out_tile_fast);
+    PassFn f = pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
                                d.lds_bytes);
@@ -176,9 +281,9 @@ hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d)
 hipError_t launch_pass(bool fp64, const PassDesc& d, const PassArgs& a, hipStream_t s)
 {
     if (d.mfma) return launch_mfma(d, a, s);
-    PassFn f = pass_fn_lookup(fp64, d.lgn, d.in_tile_fast, d.out_tile_fast);
+    PassFn f = pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(unsigned(d.blocks)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);
+    hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);
     return hipGetLastError();
 }
 

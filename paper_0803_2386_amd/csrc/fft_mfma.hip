@@ -22,7 +22,8 @@
 //   B (32 x 16): lane l holds B[8 (l / 16) + i][l % 16], i < 8
 //   D (16 x 16): lane l holds D[4 (l / 16) + i][l % 16], i < 4
 // so lane l of a group owns points 4g..4g+3 (g = l / 16) of butterfly l % 16
-// on input and frequencies {2g, 2g+1, 8+2g, 9+2g} on output.
+// on input and frequencies {2g, 2g+1, 8+2g, 9+2g} on output.  A wave works
+// on 8 groups of 16 butterflies per stage (32 points per thread).
 #include "fft_device.h"
 
 namespace moa {
@@ -49,18 +50,6 @@ template <> struct SplitT<2> {
     }
 };
 
-template <typename R, typename V>
-__device__ __forceinline__ V mfma_inter_twiddle(const PassArgs& a, int64_t d0, int k, R sign)
-{
-    const uint64_t mask = (uint64_t(1) << a.tw_lgroot) - 1;
-    const uint64_t e = (uint64_t(d0) * uint64_t(k)) & mask;
-    const V* hi = reinterpret_cast<const V*>(a.tw_hi);
-    const V* lo = reinterpret_cast<const V*>(a.tw_lo);
-    V w = cmul(hi[e >> a.tw_lglo], lo[e & ((uint64_t(1) << a.tw_lglo) - 1)]);
-    w.y = -sign * w.y;
-    return w;
-}
-
 // Entry (row, col) of the real 32 x 32 DFT matrix.
 __device__ __forceinline__ double dft32_entry(int row, int col, float sign)
 {
@@ -82,9 +71,13 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
     constexpr int NST = LGN / 4;  // radix-16 stages, all on the matrix cores
     static_assert(LGN % 4 == 0 && LGN >= 4, "matrix-core levels are powers of 16");
     constexpr int NB = N / 16;    // butterflies per column per stage
+    constexpr int GPW = 8;        // butterfly groups per wave
+    constexpr int PPT = 32;       // points per thread
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
+    V* tl = lds + a.data_elems;   // in-block twiddles (256)
+    V* tt = tl + kTwBlkEntries;   // inter-level twiddles (256 per part)
     const float sign = a.sign;
     const int lgw = a.lgw, W = 1 << lgw;
     const int t = threadIdx.x, T = blockDim.x;
@@ -114,20 +107,38 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
         ob += idx * a.out_s[d];
     }
 
-    // Coalesced copy of the tile into LDS along whichever axis is unit-stride.
+    {
+        const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
+        for (int i = threadIdx.x; i < kTwBlkEntries; i += blockDim.x) tl[i] = g1[i];
+        const V* g2 = reinterpret_cast<const V*>(a.tw_inter);
+        for (int i = threadIdx.x; i < 256 * a.tw_parts; i += blockDim.x) tt[i] = g2[i];
+    }
+    // Coalesced copy of the tile into LDS along whichever axis is unit-stride;
+    // each thread moves PPT points (T = W N / PPT) and issues all its loads
+    // before the first LDS store.
     {
         const V* __restrict__ src = reinterpret_cast<const V*>(a.in) + ib;
         const bool tf = a.in_s[0] == 1 && W > 1;
-        for (int i = t; i < (W << LGN); i += T) {
-            int w, e;
-            if (tf) {
-                w = i & (W - 1);
-                e = i >> lgw;
-            } else {
-                e = i & (N - 1);
-                w = i >> LGN;
+#pragma unroll
+        for (int half = 0; half < PPT / 16; ++half) {
+            V tmp[16];
+            int slot[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int i = t + (half * 16 + m) * T;
+                int w, e;
+                if (tf) {
+                    w = i & (W - 1);
+                    e = i >> lgw;
+                } else {
+                    e = i & (N - 1);
+                    w = i >> LGN;
+                }
+                slot[m] = w * cs + lds_pad(e);
+                tmp[m] = src[int64_t(w) * a.in_s[0] + int64_t(e) * a.in_s_e];
             }
-            lds[w * cs + lds_pad(e)] = src[int64_t(w) * a.in_s[0] + int64_t(e) * a.in_s_e];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) lds[slot[m]] = tmp[m];
         }
     }
 
@@ -144,7 +155,6 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
             ahi[h][i] = hi;
             alo[h][i] = S(float(v - double(float(hi))));
         }
-    const V* __restrict__ twb = reinterpret_cast<const V*>(a.tw_blk);
     __syncthreads();
 
 #pragma unroll
@@ -154,11 +164,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
         // Exact power-of-two scaling for fp16 (see the file comment).
         const int lgscale = PREC == 2 ? (a.pre_lg + lgns) / 2 : 0;
         const float down = __builtin_ldexpf(1.0f, -lgscale), up = __builtin_ldexpf(1.0f, lgscale);
-        V y[4][4];
-        int bidx[4], widx[4];
+        V y[GPW][4];
+        int bidx[GPW], widx[GPW];
 #pragma unroll
-        for (int grp = 0; grp < 4; ++grp) {
-            const int bf = wave * 64 + grp * 16 + (lane & 15);  // flat butterfly index of this group
+        for (int grp = 0; grp < GPW; ++grp) {
+            const int bf = wave * (16 * GPW) + grp * 16 + (lane & 15);  // flat butterfly index
             const int w = bf >> (LGN - 4), b = bf & (NB - 1);
             bidx[grp] = b;
             widx[grp] = w;
@@ -170,7 +180,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
                 V x = col[lds_pad(b + r * NB)];
                 if (s > 0) {
                     const int e = ((b & (ns - 1)) * r) << (kLgTwBlk - lgns - 4);
-                    V tw = twb[e];
+                    V tw = tw_blk(tl, e);
                     tw.y = -sign * tw.y;
                     x = cmul(x, tw);
                 }
@@ -193,7 +203,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
         }
         __syncthreads();
 #pragma unroll
-        for (int grp = 0; grp < 4; ++grp) {
+        for (int grp = 0; grp < GPW; ++grp) {
             const int b = bidx[grp];
             V* col = lds + widx[grp] * cs;
             const int base = ((b >> lgns) << (lgns + 4)) + (b & (ns - 1));
@@ -206,22 +216,39 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
         __syncthreads();
     }
 
-    // Copy out along the output's unit-stride axis, with the inter-level twiddle.
+    // Copy out along the output's unit-stride axis, with the inter-level
+    // twiddle; each thread's loads (LDS and twiddle tables) all precede its
+    // stores.
     {
         V* __restrict__ dst = reinterpret_cast<V*>(a.out) + ob;
         const bool tf = a.out_s[0] == 1 && W > 1;
-        for (int i = t; i < (W << LGN); i += T) {
-            int w, k;
-            if (tf) {
-                w = i & (W - 1);
-                k = i >> lgw;
-            } else {
-                k = i & (N - 1);
-                w = i >> LGN;
+#pragma unroll
+        for (int half = 0; half < PPT / 16; ++half) {
+            V v[16];
+            int wi[16], ki[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int i = t + (half * 16 + m) * T;
+                if (tf) {
+                    wi[m] = i & (W - 1);
+                    ki[m] = i >> lgw;
+                } else {
+                    ki[m] = i & (N - 1);
+                    wi[m] = i >> LGN;
+                }
+                v[m] = lds[wi[m] * cs + lds_pad(ki[m])];
             }
-            V v = lds[w * cs + lds_pad(k)];
-            if (a.tw) v = cmul(v, mfma_inter_twiddle<float, V>(a, d0 + w, k, sign));
-            dst[int64_t(w) * a.out_s[0] + int64_t(k) * a.out_s_k] = v;
+            if (a.tw_parts) {
+                const uint64_t mask = (uint64_t(1) << a.tw_lgroot) - 1;
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    V tw = tw_inter(tt, a.tw_parts, (uint64_t(d0 + wi[m]) * uint64_t(ki[m])) & mask);
+                    tw.y = -sign * tw.y;
+                    v[m] = cmul(v[m], tw);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 16; ++m) dst[int64_t(wi[m]) * a.out_s[0] + int64_t(ki[m]) * a.out_s_k] = v[m];
         }
     }
 }
@@ -254,7 +281,7 @@ hipError_t launch_mfma(const PassDesc& d, const PassArgs& a, hipStream_t s)
 {
     PassFn f = mfma_lookup(d.lgn, d.mfma);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(unsigned(d.blocks)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);
+    hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);
     return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ struct moa_fft_plan_s {
     std::vector<BatchTask> tasks;
     std::vector<int64_t> toff;
     std::vector<std::pair<int, int>> size_ranges;  // (first task, tasks) per distinct size
-    int batch_threads = 0, batch_lds = 0, batch_grid = 0;
+    int batch_threads = 0, batch_lds = 0, batch_grid = 0, batch_data_elems = 0;
     // tables: element offsets in d_tables (units of one complex element)
     std::vector<double> tab_host;  // interleaved re/im, float64
     int64_t tw_blk_off = 0;
@@ -95,6 +95,7 @@ struct moa_fft_plan_s {
     void* d_tasks = nullptr;
     void* d_toff = nullptr;
     int device = -1;
+    int cus = 256;                 // compute units of the device (for persistent grids)
     std::vector<GraphEntry> graphs;
     std::mutex mu;
 };
@@ -103,7 +104,7 @@ namespace {
 
 size_t elem_bytes(bool fp64) { return fp64 ? 16 : 8; }
 int max_lg_block(bool fp64) { return fp64 ? moa::kMaxLgBlockC128 : moa::kMaxLgBlockC64; }
-int max_threads(bool fp64) { return fp64 ? 512 : moa::kMaxThreads; }
+int max_threads(bool) { return moa::kMaxThreads; }
 
 // Append omega_L^e for e in [first, first + count) scaled by `step` to the
 // host table; returns the element offset of the first entry.
@@ -120,16 +121,36 @@ int64_t add_table(moa_fft_plan_s* p, int64_t L, int64_t count, int64_t step)
     return off;
 }
 
-int lgE(int lgn) { return lgn < moa::kLgE ? lgn : moa::kLgE; }
+int lgE(int lgn, int lge) { return lgn < lge ? lgn : lge; }
 
 // Fill launch fields of a pass: tile width, mapping, LDS tile, grid.
 // Matrix-core levels use one thread per 16 points like the VALU kernel, and
 // need whole waves: at least 1024 points per workgroup.
-moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w)
+moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
 {
     const int lgn = d.lgn;
-    const int tpc = 1 << (lgn - lgE(lgn));
-    const int min_lgw = d.mfma ? std::max(0, 10 - lgn) : 0;
+    const int maxT = max_threads(fp64);
+    // Points per thread: 16, or 32 when 16 would need more than maxT threads
+    // (complex64 only); the matrix-core kernel always holds 32.
+    const bool in_tf = (d.in_s[0] == 1 && d.in_s_e != 1);
+    const bool out_tf = (d.out_s[0] == 1 && d.out_s_k != 1);
+    // Level-kernel variant for a tile of 2^(lgn+lgw) points: 16 points a
+    // thread up to 512 threads (mode 0); beyond, 32 points a thread when the
+    // level stores in its load pattern (mode 1), else 16 points a thread on
+    // up to 1024 threads (mode 2).
+    auto big = [&](int lgw) { return ((int64_t(1) << (lgn + lgw)) >> 4) > maxT; };
+    auto kmode_for = [&](int lgw) {
+        if (d.mfma || fp64 || !big(lgw)) return 0;
+        const bool tf = lgw > 0;
+        return ((tf && in_tf) == (tf && out_tf)) ? 1 : 2;
+    };
+    auto lge_for = [&](int lgw) {
+        if (d.mfma) return 5;
+        return kmode_for(lgw) == 1 ? 5 : 4;
+    };
+    auto maxT_for = [&](int lgw) { return kmode_for(lgw) == 2 ? 1024 : maxT; };
+    auto tpc_for = [&](int lgw) { return 1 << (lgn - lgE(lgn, lge_for(lgw))); };
+    const int min_lgw = d.mfma ? std::max(0, 11 - lgn) : 0;
     // A lone digit 0 may have any size: its tiles must divide it.
     int lg0 = d.lg[0];
     if (d.nd == 1) {
@@ -137,44 +158,70 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w)
         while ((d.size[0] % (int64_t(2) << lg0)) == 0) ++lg0;
     }
     const int eb = int(elem_bytes(fp64));
-    const int maxT = max_threads(fp64);
+    const int table_bytes = (moa::kTwBlkEntries + 256 * d.tw_parts) * eb;
     auto lds_for = [&](int lgw, bool tile_fast) {
         const int W = 1 << lgw;
-        const int lanes = tile_fast ? (W >= 16 ? 1 : 16 / W) : tpc;
+        const int lanes = tile_fast ? (W >= 16 ? 1 : 16 / W) : tpc_for(lgw);
         const int cs = moa::lds_col_stride(1 << lgn, lanes);
-        return std::make_pair(cs, W * cs * eb);
+        return std::make_pair(cs, W * cs * eb + table_bytes);
     };
-    const bool in_tf = (d.in_s[0] == 1 && d.in_s_e != 1);
-    const bool out_tf = (d.out_s[0] == 1 && d.out_s_k != 1);
+    // The matrix-core kernel always runs 32 points a thread (W N / 32 threads).
+    auto threads_for = [&](int lgw) -> int64_t {
+        if (d.mfma) return (int64_t(1) << (lgn + lgw)) >> 5;
+        return (int64_t(1) << lgw) * tpc_for(lgw);
+    };
+    auto threads_ok = [&](int lgw) { return threads_for(lgw) <= maxT_for(lgw); };
     int lgw = 0;
     if (want_w > 0) {
         if (!is_pow2(want_w)) return MOA_ERR_TUNING;
         lgw = lg2(want_w);
         if (lgw > lg0 || lgw < min_lgw) return MOA_ERR_TUNING;
-        if ((int64_t(1) << lgw) * tpc > maxT) return MOA_ERR_TUNING;
+        if (!threads_ok(lgw)) return MOA_ERR_TUNING;
         if (lds_for(lgw, in_tf && lgw > 0).second > moa::kLdsBytes) return MOA_ERR_TUNING;
     } else {
-        // Default: as many columns as fit 2^14 (c64) / 2^13 (c128) points,
-        // the thread limit and LDS, and the digit itself.
-        const int target_lg = fp64 ? 13 : 14;
+        // Default tile: 2^12 points (2^11 for c128), so that several
+        // workgroups share a CU and overlap each other's memory phases; a
+        // tile whose digit 0 is a unit-stride side takes at least 4 columns
+        // (32-byte segments, the narrowest the L2 merges well), up to the
+        // thread limit, LDS and the digit itself.
+        const int base_lg = fp64 ? 11 : 12;
+        const int target_lg = (in_tf || out_tf) ? std::max(base_lg, lgn + 2) : base_lg;
         lgw = std::min(min_lgw, lg0);
-        while (lgw < lg0 && lgn + lgw + 1 <= target_lg && (int64_t(2) << lgw) * tpc <= maxT &&
+        while (lgw < lg0 && lgn + lgw + 1 <= std::max(target_lg, lgn + min_lgw) && threads_ok(lgw + 1) &&
                lds_for(lgw + 1, in_tf).second <= moa::kLdsBytes)
             ++lgw;
     }
     if (lgw < min_lgw) return MOA_ERR_LIFT;  // matrix-core level with too few transforms
     d.lgw = lgw;
+    d.lge = lge_for(lgw);
+    d.kmode = kmode_for(lgw);
     d.in_tile_fast = lgw > 0 && in_tf;
     d.out_tile_fast = lgw > 0 && out_tf;
     const auto cl = lds_for(lgw, d.in_tile_fast);
     d.col_stride = cl.first;
-    d.lds_bytes = cl.second;
-    d.threads = (1 << lgw) * tpc;
+    d.data_elems = (1 << lgw) * cl.first;
+    // LDS: data tile, then the in-block twiddle halves, then the inter-level parts.
+    d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * d.tw_parts) * eb;
+    if (d.lds_bytes > moa::kLdsBytes) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
+    d.threads = int(threads_for(lgw));
+    if (!threads_ok(lgw)) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
     int64_t blocks = d.size[0] >> lgw;
     for (int i = 1; i < d.nd; ++i) blocks *= d.size[i];
     if (blocks >= (int64_t(1) << 31)) return MOA_ERR_BATCH;
     d.blocks = blocks;
-    d.xcd_remap = (blocks % 8 == 0 && blocks >= 16) ? 1 : 0;
+    if (d.mfma || d.kmode == 2) {
+        d.grid = blocks;  // one tile per workgroup
+        d.xcd_remap = (blocks % 8 == 0 && blocks >= 16) ? 1 : 0;
+    } else {
+        // Persistent grid: the workgroups that fit at once (LDS and a
+        // 1024-lane-per-CU register budget), a multiple of 8 so each XCD
+        // walks its own contiguous run of tiles.
+        const int per_cu = std::max(1, std::min(moa::kLdsBytes / d.lds_bytes, std::max(1, 1024 / d.threads)));
+        int64_t g = std::min<int64_t>(blocks, int64_t(cus) * per_cu);
+        if (g >= 8) g &= ~int64_t(7);
+        d.grid = std::max<int64_t>(g, 1);
+        d.xcd_remap = (d.grid % 8 == 0 && blocks >= 16) ? 1 : 0;
+    }
     return MOA_OK;
 }
 
@@ -223,7 +270,7 @@ moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
             if (B > 1) push_digit(d, B, n, n);
             d.tw = 1;
             d.tw_lgroot = lg2(D[size_t(l)] * Rl);
-            d.tw_lglo = (d.tw_lgroot + 1) / 2;
+            d.tw_parts = (d.tw_lgroot + 7) / 8;
         } else {
             d.in_s_e = Rs[size_t(l)];
             d.out_s_k = Xs[size_t(l)];
@@ -235,25 +282,35 @@ moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         if (p->prec != MOA_FFT_PREC_NATIVE && d.lgn % 4 == 0 && d.lgn >= 4 && d.lgn <= 12) d.mfma = p->prec;
         const int want = tuning ? tuning->cols_per_block[l] : 0;
         if (tuning && (want < 0)) return MOA_ERR_TUNING;
-        moa_status_t st = finish_pass(d, p->fp64, want);
+        moa_status_t st = finish_pass(d, p->fp64, want, p->cus);
         if (st != MOA_OK) return st;
+        // The level kernel applies the inter-level factor only when it stores
+        // in its load pattern, which every non-final level of this lowering does.
+        if (d.tw && !d.mfma && d.in_tile_fast != d.out_tile_fast) return MOA_ERR_STATE;
         p->passes.push_back(d);
     }
     return MOA_OK;
 }
 
+// In-block table: omega_{2^14}^e for e < 128, then omega_{2^14}^(128 e) for
+// e < 128.  Inter-level tables of a level with root 2^R: part p holds
+// omega_{2^R}^(e 2^(8p)) for e < 256.
+int64_t add_block_table(moa_fft_plan_s* p)
+{
+    const int64_t off = add_table(p, int64_t(1) << 14, 128, 1);
+    add_table(p, int64_t(1) << 14, 128, 128);
+    return off;
+}
+
 void build_tables(moa_fft_plan_s* p)
 {
     p->tab_host.clear();
-    // In-block table: omega_{2^14}^e, e < 2^14.
-    p->tw_blk_off = add_table(p, int64_t(1) << 14, int64_t(1) << 14, 1);
+    p->tw_blk_off = add_block_table(p);
     for (PassDesc& d : p->passes) {
         if (!d.tw) continue;
         const int64_t root = int64_t(1) << d.tw_lgroot;
-        const int64_t nlo = int64_t(1) << d.tw_lglo;
-        const int64_t nhi = root / nlo;
-        d.tw_lo_off = add_table(p, root, nlo, 1);
-        d.tw_hi_off = add_table(p, root, nhi, nlo);
+        d.tw_inter_off = add_table(p, root, 256, 1);
+        for (int part = 1; part < d.tw_parts; ++part) add_table(p, root, 256, int64_t(1) << (8 * part));
     }
 }
 
@@ -360,11 +417,14 @@ std::string describe_json(const moa_fft_plan_s* p)
         for (int i = 0; i < d.nd; ++i)
             add("%s{\"size\":%lld,\"in_stride\":%lld,\"out_stride\":%lld}", i ? "," : "",
                 (long long)d.size[i], (long long)d.in_s[i], (long long)d.out_s[i]);
-        add("],\"twiddle_root\":%lld,\"tile_width\":%d,\"threads\":%d,\"blocks\":%lld,\"lds_bytes\":%d,"
-            "\"lds_col_stride\":%d,\"in_tile_fast\":%s,\"out_tile_fast\":%s,\"xcd_remap\":%d,\"mfma\":\"%s\"}",
-            d.tw ? (long long)(int64_t(1) << d.tw_lgroot) : 0LL, 1 << d.lgw, d.threads, (long long)d.blocks,
+        add("],\"twiddle_root\":%lld,\"twiddle_parts\":%d,\"grid\":%lld,\"tile_width\":%d,\"threads\":%d,\"blocks\":%lld,\"lds_bytes\":%d,"
+            "\"lds_col_stride\":%d,\"in_tile_fast\":%s,\"out_tile_fast\":%s,\"xcd_remap\":%d,\"mfma\":\"%s\","
+            "\"points_per_thread\":%d,\"kernel_mode\":%d}",
+            d.tw ? (long long)(int64_t(1) << d.tw_lgroot) : 0LL, d.tw ? d.tw_parts : 0, (long long)d.grid, 1 << d.lgw,
+            d.threads, (long long)d.blocks,
             d.lds_bytes, d.col_stride, d.in_tile_fast ? "true" : "false", d.out_tile_fast ? "true" : "false",
-            d.xcd_remap, d.mfma == 0 ? "none" : (d.mfma == 1 ? "split_bf16" : "split_fp16"));
+            d.xcd_remap, d.mfma == 0 ? "none" : (d.mfma == 1 ? "split_bf16" : "split_fp16"),
+            d.mfma ? 32 : (1 << lgE(d.lgn, d.lge)), d.kmode);
     }
     s += "]";
     if (p->batched) {
@@ -410,12 +470,12 @@ void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, std:
         a.lgw = d.lgw;
         a.lg_tiles = d.nd == 1 ? 0 : d.lg[0] - d.lgw;
         a.col_stride = d.col_stride;
-        a.tw = d.tw;
+        a.tw_parts = d.tw ? d.tw_parts : 0;
         a.tw_lgroot = d.tw_lgroot;
-        a.tw_lglo = d.tw_lglo;
-        a.tw_hi = tb + size_t(d.tw_hi_off) * eb;
-        a.tw_lo = tb + size_t(d.tw_lo_off) * eb;
+        a.tw_inter = tb + size_t(d.tw_inter_off) * eb;
         a.tw_blk = tb + size_t(p->tw_blk_off) * eb;
+        a.ntiles = d.blocks;
+        a.data_elems = d.data_elems;
         a.xcd_remap = d.xcd_remap;
         a.pre_lg = d.pre_lg;
         a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
@@ -434,6 +494,7 @@ moa::BatchArgs batch_args(const moa_fft_plan_s* p, int dir, const void* in, void
     a.tw_blk = static_cast<const unsigned char*>(p->d_tables) + size_t(p->tw_blk_off) * elem_bytes(p->fp64);
     a.task0 = task0;
     a.ntasks = ntasks;
+    a.data_elems = p->batch_data_elems;
     a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
     return a;
 }
@@ -506,7 +567,7 @@ moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, G
         pass_args(p, dir, in, out, args);
         for (size_t l = 0; l < p->passes.size() && st == MOA_OK; ++l) {
             const PassDesc& d = p->passes[l];
-            st = add_node(g.graph, &prev, moa::pass_kernel_fn(p->fp64, d), dim3(unsigned(d.blocks)),
+            st = add_node(g.graph, &prev, moa::pass_kernel_fn(p->fp64, d), dim3(unsigned(d.grid)),
                           dim3(unsigned(d.threads)), d.lds_bytes, &args[l]);
         }
     }
@@ -543,7 +604,7 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     for (int lg = maxlg; lg >= 0; --lg) {
         const auto& idx = by_lg[size_t(lg)];
         if (idx.empty()) continue;
-        const int tpc = 1 << (lg - lgE(lg));
+        const int tpc = 1 << (lg - lgE(lg, lg >= 14 ? 5 : 4));
         const int cs = moa::lds_col_stride(1 << lg, tpc);
         // LDS of one full tile: 2^14 complex64 or 2^13 complex128 points.
         const int64_t budget = int64_t(moa::lds_padded_len(1 << maxlg)) * int64_t(eb);
@@ -564,7 +625,9 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     }
     // Within a size the full tasks come first; sizes are already longest first.
     p->batch_threads = T;
-    p->batch_lds = std::max(lds_max, 16);
+    // LDS: data tile, in-block twiddle table, two task-offset buffers.
+    p->batch_data_elems = int(lds_max / int64_t(eb));
+    p->batch_lds = lds_max + moa::kTwBlkEntries * int(eb) + 2 * moa::kMaxTaskCols * int(sizeof(int64_t));
     int grid = int(p->tasks.size());
     if (tuning && tuning->persistent_blocks < 0) return MOA_ERR_TUNING;
     if (tuning && tuning->persistent_blocks > 0) {
@@ -660,6 +723,12 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
     p->total = n * batch;
     p->lift = lift;
     p->levels.assign(lift.rbegin(), lift.rend());
+    if (!p->host_only) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->cus = cus;
+    }
     st = lower(p, tuning);
     if (st != MOA_OK) {
         delete p;
@@ -697,7 +766,7 @@ moa_status_t moa_fft_plan_batched_tuned(moa_fft_plan_t* out, const int64_t* size
         return st;
     }
     p->tab_host.clear();
-    p->tw_blk_off = add_table(p, int64_t(1) << 14, int64_t(1) << 14, 1);
+    p->tw_blk_off = add_block_table(p);
     return finalize(p, out);
 }
 

@@ -1,0 +1,188 @@
+"""Autotuner: picks the lift and the per-level tile widths of a plan by timing
+candidates on the device, and the persistent grid of an uneven batch.
+
+The paper leaves the blocking size c as a run-time parameter to be chosen per
+machine (Ch. 1 and Ch. 3, "Results and Discussion": the best c was found by
+experiment, not from the cache size).  Here the candidates are lifts whose
+levels each fit one workgroup, in the paper's uniform form
+<2^p_max c ... c> and in balanced mixed forms, each with a few tile widths;
+every candidate is planned through the C ABI, timed with HIP events, and the
+fastest is cached in a JSON file keyed by device, dtype, n and batch
+(``$MOA_FFT_TUNE_CACHE``, default ``~/.cache/moa_fft_tune.json``).  Timing is
+the only thing done here; all arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import threading
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+from . import capi
+
+_lock = threading.Lock()
+
+
+def cache_path() -> str:
+    return os.environ.get("MOA_FFT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                             "moa_fft_tune.json"))
+
+
+def _load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c: dict) -> None:
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _key(device_name: str, dtype_code: int, n: int, batch: int, prec: int) -> str:
+    return f"{device_name}|{'c64' if dtype_code == capi.MOA_C64 else 'c128'}|p{prec}|n{n}|b{batch}"
+
+
+def lift_candidates(n: int, dtype_code: int = capi.MOA_C64, max_levels: int = 3) -> List[List[int]]:
+    """Lifts (outermost factor first) whose levels fit one workgroup: the
+    paper's uniform blocking <2^p_max c ... c> for every c, plus all
+    factorizations into at most `max_levels` powers of two."""
+    d = n.bit_length() - 1
+    maxlg = capi.moa_fft_max_block(dtype_code).bit_length() - 1
+    out = set()
+    if d <= maxlg:
+        out.add((n,))
+    for lam in range(1, maxlg + 1):        # paper's uniform block c = 2^lam
+        if lam >= d:
+            continue
+        l_max = -(-d // lam) - 1
+        p_max = d - l_max * lam
+        if l_max + 1 <= max_levels:
+            out.add(tuple([1 << p_max] + [1 << lam] * l_max))
+    for L in range(2, max_levels + 1):       # mixed factorizations
+        for parts in itertools.product(range(1, maxlg + 1), repeat=L):
+            if sum(parts) == d:
+                out.add(tuple(1 << p for p in parts))
+    return sorted((list(c) for c in out), key=lambda c: (len(c), c))
+
+
+def _plan_ok(n, batch, lift, dtype_code, prec, tuning) -> Optional[dict]:
+    try:
+        h = capi.moa_fft_plan(n, batch, lift, dtype_code, prec, capi.MOA_FFT_FLAG_HOST_ONLY, tuning)
+    except capi.MoaError:
+        return None
+    try:
+        return json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+
+
+def candidates(n: int, batch: int, dtype_code: int = capi.MOA_C64, prec: int = capi.MOA_FFT_PREC_NATIVE,
+               max_levels: int = 3, widths: Sequence[int] = (0, 1, 2, 4, 8, 16, 32, 64)) -> List[Tuple[List[int], dict]]:
+    """(lift, tuning) pairs that plan successfully (host-only validation)."""
+    out = []
+    for lift in lift_candidates(n, dtype_code, max_levels):
+        L = len(lift)
+        for w in widths:
+            tuning = {"cols_per_block": [w] * L} if w else None
+            if _plan_ok(n, batch, lift, dtype_code, prec, tuning) is not None:
+                out.append((lift, tuning))
+    return out
+
+
+def _time_plan(torch, plan, x, out, reps: int) -> float:
+    for _ in range(2):
+        plan.forward(x, out=out)
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        plan.forward(x, out=out)
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: int = 3, reps: int = 10,
+         candidates_limit: Optional[int] = None, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Time the candidate lifts/tile widths for (n, batch) on the current
+    device; returns {"lift", "tuning", "ms", "tried"} and caches it."""
+    import torch
+
+    from . import fft as mfft
+    dtype = dtype or torch.complex64
+    dcode = mfft._dtype_code(dtype)
+    pcode = mfft._PREC[prec]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    name = torch.cuda.get_device_name(dev)
+    key = _key(name, dcode, n, batch, pcode)
+    if use_cache:
+        with _lock:
+            hit = _load_cache().get(key)
+        if hit:
+            return hit
+    cands = candidates(n, batch, dcode, pcode, max_levels)
+    if candidates_limit:
+        cands = cands[:candidates_limit]
+    real = torch.float32 if dtype == torch.complex64 else torch.float64
+    x = torch.zeros(2 * n * batch, dtype=real, device=dev).view(dtype)
+    out = torch.empty_like(x)
+    best = None
+    tried = 0
+    for lift, tuning in cands:
+        plan = mfft.Plan(n, batch, lift, dtype=dtype, prec=prec, tuning=tuning)
+        ms = _time_plan(torch, plan, x, out, reps)
+        plan.close()
+        tried += 1
+        if verbose:
+            print(f"tune n={n} batch={batch} lift={lift} tuning={tuning}: {ms:.4f} ms", flush=True)
+        if best is None or ms < best["ms"]:
+            best = {"lift": lift, "tuning": tuning, "ms": ms}
+    best["tried"] = tried
+    if use_cache:
+        with _lock:
+            c = _load_cache()
+            c[key] = best
+            _save_cache(c)
+    return best
+
+
+def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 128, 256, 384, 512, 768, 1024),
+                 reps: int = 10, verbose: bool = False) -> dict:
+    """Time the persistent grid of an uneven batch; returns the best tuning."""
+    import torch
+
+    from . import fft as mfft
+    dtype = dtype or torch.complex64
+    dev = torch.device("cuda", torch.cuda.current_device())
+    total = int(sum(sizes))
+    real = torch.float32 if dtype == torch.complex64 else torch.float64
+    x = torch.zeros(2 * total, dtype=real, device=dev).view(dtype)
+    out = torch.empty_like(x)
+    best = None
+    for g in grids:
+        tuning = {"persistent_blocks": int(g)} if g else None
+        plan = mfft.BatchedPlan(sizes, dtype=dtype, tuning=tuning)
+        ms = _time_plan(torch, plan, x, out, reps)
+        grid = plan.describe()["persistent_blocks"]
+        plan.close()
+        if verbose:
+            print(f"tune batched grid={grid}: {ms:.4f} ms", flush=True)
+        if best is None or ms < best["ms"]:
+            best = {"tuning": tuning, "grid": grid, "ms": ms}
+    return best
+
+
+def tuned_plan(n: int, batch: int = 1, dtype=None, prec: str = "native", **kw):
+    """A Plan with the tuned lift and tile widths (tuning on first use)."""
+    from . import fft as mfft
+    r = tune(n, batch, dtype, prec, **kw)
+    import torch
+    return mfft.Plan(n, batch, r["lift"], dtype=dtype or torch.complex64, prec=prec, tuning=r["tuning"])

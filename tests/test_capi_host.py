@@ -222,4 +222,4 @@ def test_batched_plan_partitions_the_transforms():
     groups = d["sizes_by_task_group"]
     assert [g["n"] for g in groups] == sorted(set(sizes), reverse=True)
     assert sum(g["tasks"] for g in groups) == d["tasks"]
-    assert d["lds_bytes"] <= 160 * 1024 and d["threads"] == 1024
+    assert d["lds_bytes"] <= 160 * 1024 and d["threads"] == 512

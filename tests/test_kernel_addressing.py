@@ -25,20 +25,37 @@ def pad(i):
 
 def check_pass(p, total, elem_bytes):
     N = p["N"]
-    lgn = N.bit_length() - 1
-    E = 1 << lg_e(lgn)
+    mfma = p["mfma"] != "none"
+    E = min(N, p["points_per_thread"]) if not mfma else 1
     TPC = N // E
     W = p["tile_width"]
     T = p["threads"]
-    assert T == W * TPC and T <= 1024
+    if mfma:
+        # 32 points a thread, copied in and out over i = t + m T
+        assert T * 32 == W * N and T % 64 == 0 and T <= 512
+        T = W * N  # check the full (column, row) set below
+    else:
+        assert T == W * TPC and T <= (1024 if p["kernel_mode"] == 2 else 512)
     axes = p["batch_axes"]
     nd = len(axes)
     blocks = p["blocks"]
     bid = np.arange(blocks, dtype=np.int64)
-    if p["xcd_remap"]:
+    if p["xcd_remap"] and p["grid"] == blocks:
+        # one tile per workgroup: the remap must be a permutation of the tiles
         assert blocks % 8 == 0
         bid = (bid & 7) * (blocks >> 3) + (bid >> 3)
         assert np.array_equal(np.sort(bid), np.arange(blocks))
+    elif p["xcd_remap"]:
+        # persistent grid: XCD x walks tiles [x*chunk, (x+1)*chunk) with the
+        # grid/8 workgroups it holds; together they must cover every tile once
+        G = p["grid"]
+        assert G % 8 == 0
+        chunk = (blocks + 7) // 8
+        seen = []
+        for b in range(G):
+            x, lw = b & 7, b >> 3
+            seen.extend(range(x * chunk + lw, min(blocks, (x + 1) * chunk), G // 8))
+        assert sorted(seen) == list(range(blocks))
     if nd == 1:
         tile, rest = bid, np.zeros_like(bid)
         assert blocks * W == axes[0]["size"]
@@ -95,6 +112,22 @@ def check_pass(p, total, elem_bytes):
 ])
 def test_pass_kernel_geometry(n, batch, lift, dtype):
     h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST)
+    _check_plan(h, n, batch, dtype)
+
+
+@pytest.mark.parametrize("prec", [capi.MOA_FFT_PREC_SPLIT_BF16, capi.MOA_FFT_PREC_SPLIT_FP16])
+@pytest.mark.parametrize("n,batch,lift", [(1 << 20, 4, [256, 4096]), (256, 64, None), (4096, 4, None),
+                                          (1 << 16, 2, [16, 4096]), (1 << 16, 2, [256, 256]),
+                                          (1 << 12, 3, [16, 256]), (1 << 20, 2, [256, 4096])])
+def test_mfma_pass_geometry(n, batch, lift, prec):
+    h = capi.moa_fft_plan(n, batch, lift, prec=prec, flags=HOST)
+    d = _check_plan(h, n, batch, capi.MOA_C64)
+    for p in d["passes"]:
+        if p["mfma"] != "none":
+            assert p["threads"] % 64 == 0 and p["threads"] == p["tile_width"] * p["N"] // 32
+
+
+def _check_plan(h, n, batch, dtype):
     try:
         d = json.loads(capi.moa_fft_describe(h))
     finally:
@@ -102,6 +135,7 @@ def test_pass_kernel_geometry(n, batch, lift, dtype):
     eb = 8 if dtype == capi.MOA_C64 else 16
     for p in d["passes"]:
         check_pass(p, n * batch, eb)
+    return d
 
 
 @pytest.mark.parametrize("cols", [1, 2, 4, 8, 16, 32, 64])
@@ -131,11 +165,11 @@ def test_batched_task_geometry():
     for g in d["sizes_by_task_group"]:
         N = g["n"]
         lgn = N.bit_length() - 1
-        TPC = N >> lg_e(lgn)
+        TPC = N >> min(lgn, 5 if lgn >= 14 else 4)
         lanes = TPC
         base = N + (N >> 4)
         cs = base if lanes >= 16 else base + ((lanes - (base & 31) + 32) & 31)
-        per = min(1024 // TPC, (17408 * 8) // (cs * 8))
+        per = min(512 // TPC, (17408 * 8) // (cs * 8))
         assert per * TPC <= d["threads"]
-        assert per * cs * 8 <= d["lds_bytes"] <= 160 * 1024
+        assert per * cs * 8 + 256 * 8 + 2 * 512 * 8 <= d["lds_bytes"] <= 160 * 1024
     assert d["tasks"] == sum(g["tasks"] for g in d["sizes_by_task_group"])

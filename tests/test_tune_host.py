@@ -1,0 +1,30 @@
+"""Host-side tests of the autotuner's candidate space (no GPU)."""
+import numpy as np
+
+from paper_0803_2386_amd import capi, tune
+
+
+def test_lift_candidates_cover_paper_blockings():
+    n = 1 << 24
+    cands = tune.lift_candidates(n)
+    assert [4096, 4096] in cands
+    # the paper's uniform blocking n = 2^p_max c^l_max for c = 256: <256 256 256>
+    assert [256, 256, 256] in cands
+    # c = 2^12 with d = 24 gives p_max = 12: <4096 4096>; c = 2^13: <2^11 2^13>
+    assert [2048, 8192] in cands
+    for c in cands:
+        assert int(np.prod(c)) == n
+        assert all(f <= capi.moa_fft_max_block(capi.MOA_C64) for f in c)
+        assert len(c) <= 3
+
+
+def test_single_level_when_it_fits():
+    assert [1 << 12] in tune.lift_candidates(1 << 12)
+    assert all(len(c) >= 2 for c in tune.lift_candidates(1 << 14, capi.MOA_C128))
+
+
+def test_candidates_plan_on_host():
+    cands = tune.candidates(1 << 16, 4)
+    assert len(cands) > 5
+    lifts = {tuple(l) for l, _ in cands}
+    assert (256, 256) in lifts and (1 << 16,) not in lifts
