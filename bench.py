@@ -47,6 +47,39 @@ def time_events(fn, reps, torch):
     return s.elapsed_time(e) / reps
 
 
+def kernel_name(p):
+    """Device symbol (demangled) of the kernel a pass descriptor launches."""
+    lg = int(math.log2(p["N"]))
+    tin, tout = str(p["in_tile_fast"]).lower(), str(p["out_tile_fast"]).lower()
+    if p["mfma"] != "none":
+        return "k_pass_mfma<%d, %d>" % (lg, 1 if p["mfma"] == "split_bf16" else 2)
+    if p["kernel_mode"] == 3:
+        return "k_pass_pair<%d, %s, %s>" % (lg, tin, tout)
+    return "k_pass<float, %d, %d, %s, %s>" % (lg, p["kernel_mode"], tin, tout)
+
+
+def level_times_in_chain(plan, x, out, reps, torch):
+    """Average duration (ms) of each level launch run in sequence, level l
+    reading what level l - 1 wrote, with events between the launches."""
+    levels = plan.num_levels
+    bufs = [x] + [torch.empty_like(x) for _ in range(min(levels - 1, 2))]
+    chain = []
+    for lvl in range(levels):
+        src = bufs[0] if lvl == 0 else bufs[1 + (lvl - 1) % 2]
+        dst = out if lvl + 1 == levels else bufs[1 + lvl % 2]
+        chain.append((lvl, src, dst))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(levels + 1)] for _ in range(reps)]
+    for lvl, src, dst in chain:
+        plan.run_level(lvl, src, dst)
+    for r in range(reps):
+        ev[r][0].record()
+        for lvl, src, dst in chain:
+            plan.run_level(lvl, src, dst)
+            ev[r][lvl + 1].record()
+    torch.cuda.synchronize()
+    return [sum(ev[r][lvl].elapsed_time(ev[r][lvl + 1]) for r in range(reps)) / reps for lvl in range(levels)]
+
+
 def rel_err(got, want, np):
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
@@ -101,21 +134,17 @@ def main():
         copy_ms = time_events(lambda: ref.copy_(x), args.steps, torch)
         print(f"[bench] reference copy of {8 * n} B: {copy_ms:.4f} ms", file=sys.stderr, flush=True)
 
-    # Per-level kernel durations (HIP events on the launch stream).
+    # Per-level kernel durations, each level in its place in the chain
+    # x -> workspace -> ... -> out (so the cache state matches the full
+    # transform), timed by HIP events on the launch stream.
     levels = plan.num_levels
-    ws_out = torch.empty_like(x)
-    level_ms = []
-    for lvl in range(levels):
-        level_ms.append(time_events(lambda: plan.run_level(lvl, x, ws_out), args.steps, torch))
+    level_ms = level_times_in_chain(plan, x, out, args.steps, torch)
     step_event_ms = time_events(lambda: plan.forward(x, out=out), args.steps, torch)
     dom = int(np.argmax(level_ms))
     bytes_per_launch = 2 * 8 * n * batch  # read + write every element once
     achieved = bytes_per_launch / (level_ms[dom] * 1e-3) / 1e9
     desc = plan.describe()
-    kernel_names = []
-    for p in desc["passes"]:
-        kernel_names.append("k_pass<float, %d, %s, %s>" % (int(math.log2(p["N"])),
-                            str(p["in_tile_fast"]).lower(), str(p["out_tile_fast"]).lower()))
+    kernel_names = [kernel_name(p) for p in desc["passes"]]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": kernel_names[dom], "level": dom,

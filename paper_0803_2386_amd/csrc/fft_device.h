@@ -101,6 +101,31 @@ __device__ __forceinline__ void dft_reg(V* v, R sign)
     }
 }
 
+// Highest set bit of r > 0 (a constant after unrolling).
+__host__ __device__ constexpr int hibit(int r)
+{
+    int b = 0;
+    while ((r >> (b + 1)) != 0) ++b;
+    return b;
+}
+
+// Products of powers: f[r] = f0 * prod over the set bits b of r of pw[b],
+// for 0 < r < 2^LG.  Each entry is one product of an earlier entry with one
+// power, so f[r] carries popcount(r) roundings past f0 -- the same as
+// multiplying the powers in one at a time -- for RS - 1 products in all.
+// With unit f0 (ONE_BASE) the first product of each chain is skipped.
+template <int LG, bool ONE_BASE, typename V>
+__device__ __forceinline__ void power_tree(V (&f)[1 << LG], const V* pw)
+{
+#pragma unroll
+    for (int r = 1; r < (1 << LG); ++r) {
+        const int hb = hibit(r);
+        const int rest = r - (1 << hb);
+        if (ONE_BASE && rest == 0) f[r] = pw[hb];
+        else f[r] = cmul(f[rest], pw[hb]);
+    }
+}
+
 // Stage schedule of a length-2^lgn transform: radix-16 stages, then one stage
 // with the remaining radix.  A thread holds 2^lge points (16 or 32), i.e.
 // NB = 2^lge / radix butterflies of each stage.
@@ -249,6 +274,35 @@ __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V*
             __syncthreads();
             run_stages<R, LGN, LGE, S + 1, FROM_LDS>(v, col, j, sign, twb, active, tw);
         }
+    }
+}
+
+// Element offsets of tile `tile`: its first value of digit 0 and the input and
+// output offsets of the remaining digits.
+__device__ __forceinline__ void tile_offsets(const PassArgs& a, uint64_t tile_id, int64_t& d0, int64_t& ib,
+                                             int64_t& ob)
+{
+    uint64_t tile, rest;
+    if (a.nd == 1) {
+        tile = tile_id;
+        rest = 0;
+    } else {
+        tile = tile_id & ((uint64_t(1) << a.lg_tiles) - 1);
+        rest = tile_id >> a.lg_tiles;
+    }
+    d0 = int64_t(tile << a.lgw);
+    ib = d0 * a.in_s[0];
+    ob = d0 * a.out_s[0];
+    for (int d = 1; d < a.nd; ++d) {
+        int64_t idx;
+        if (d + 1 == a.nd) {
+            idx = int64_t(rest);
+        } else {
+            idx = int64_t(rest & ((uint64_t(1) << a.lg[d]) - 1));
+            rest >>= a.lg[d];
+        }
+        ib += idx * a.in_s[d];
+        ob += idx * a.out_s[d];
     }
 }
 

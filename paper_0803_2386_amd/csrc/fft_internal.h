@@ -1,5 +1,5 @@
 // Internal interfaces between the host planner (plan.cpp, psi.hpp) and the
-// gfx950 kernels (fft_kernels.hip, fft_batched.hip, fft_mfma.hip).
+// gfx950 kernels (fft_kernels.hip, fft_pair.hip, fft_batched.hip, fft_mfma.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -60,7 +60,7 @@ struct PassDesc {
     int64_t out_s[kMaxDigits] = {0};
     int lgw = 0;                  // log2 transforms per workgroup (tile width)
     int lge = kLgE;               // log2 points per thread
-    int kmode = 0;                // level kernel variant (see fft_kernels.hip)
+    int kmode = 0;                // level kernel variant (fft_kernels.hip; 3 = paired columns, fft_pair.hip)
     // Inter-level twiddle omega_{2^tw_lgroot}^(d0 * k), d0 = value of digit 0.
     int tw = 0;
     int tw_lgroot = 0;
@@ -134,6 +134,10 @@ hipError_t prepare_batched_kernel(bool fp64, int lds_bytes);
 hipError_t launch_mfma(const PassDesc& d, const PassArgs& a, hipStream_t s);
 hipError_t prepare_mfma_kernel(const PassDesc& d);
 const void* mfma_kernel_fn(const PassDesc& d);
+// Paired-column levels (fft_pair.hip): complex64, lgn in [12, 14], kmode 3.
+hipError_t launch_pair(const PassDesc& d, const PassArgs& a, hipStream_t s);
+hipError_t prepare_pair_kernel(const PassDesc& d);
+const void* pair_kernel_fn(const PassDesc& d);
 // The kernel function pointers, used to build HIP graph nodes.
 const void* pass_kernel_fn(bool fp64, const PassDesc& d);
 const void* batched_kernel_fn(bool fp64);

@@ -29,35 +29,6 @@
 
 namespace moa {
 
-// Element offsets of tile `tile`: its first value of digit 0 and the input and
-// output offsets of the remaining digits.
-__device__ __forceinline__ void tile_offsets(const PassArgs& a, uint64_t tile_id, int64_t& d0, int64_t& ib,
-                                             int64_t& ob)
-{
-    uint64_t tile, rest;
-    if (a.nd == 1) {
-        tile = tile_id;
-        rest = 0;
-    } else {
-        tile = tile_id & ((uint64_t(1) << a.lg_tiles) - 1);
-        rest = tile_id >> a.lg_tiles;
-    }
-    d0 = int64_t(tile << a.lgw);
-    ib = d0 * a.in_s[0];
-    ob = d0 * a.out_s[0];
-    for (int d = 1; d < a.nd; ++d) {
-        int64_t idx;
-        if (d + 1 == a.nd) {
-            idx = int64_t(rest);
-        } else {
-            idx = int64_t(rest & ((uint64_t(1) << a.lg[d]) - 1));
-            rest >>= a.lg[d];
-        }
-        ib += idx * a.in_s[d];
-        ob += idx * a.out_s[d];
-    }
-}
-
 // Load the points of tile `tile_id` this thread owns (slot order of stage 0).
 template <int LGN, int LGE, typename V>
 __device__ __forceinline__ void prefetch_now(const PassArgs& a, uint64_t tile_id, int64_t& d0, int64_t& ib,
@@ -266,12 +237,14 @@ static PassFn pass_fn_lookup(bool fp64, int lgn, int km, bool tin, bool tout)
 const void* pass_kernel_fn(bool fp64, const PassDesc& d)
 {
     if (d.mfma) return mfma_kernel_fn(d);
+    if (d.kmode == 3) return pair_kernel_fn(d);
     return reinterpret_cast<const void*>(pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast));
 }
 
 hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d)
 {
     if (d.mfma) return prepare_mfma_kernel(d);
+    if (d.kmode == 3) return prepare_pair_kernel(d);
     PassFn f = pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -281,6 +254,7 @@ hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d)
 hipError_t launch_pass(bool fp64, const PassDesc& d, const PassArgs& a, hipStream_t s)
 {
     if (d.mfma) return launch_mfma(d, a, s);
+    if (d.kmode == 3) return launch_pair(d, a, s);
     PassFn f = pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);

@@ -1,0 +1,248 @@
+// Paired-column level kernel for complex64 levels of 2^12 .. 2^14 points.
+//
+// A level whose tile digit is the unit-stride axis of its input or output
+// (the column FFTs of the four-step view, Ch. 3 "The General Algorithm", and
+// the final transpose of the last level) touches, per row of the tile, one
+// run of W adjacent elements.  A tile held in LDS has at most 2^14 points,
+// i.e. W = 16384 / N columns: 32-byte runs at N = 4096, and HBM serves those
+// at about half the rate of 64-byte runs (partial bursts on reads, partial
+// line writes on stores).  This kernel doubles W by keeping the tile in VGPRs:
+// each of 1024 threads owns two adjacent columns, 16 points of each, and moves
+// both with one 16-byte access on a unit-stride side.  LDS carries only the
+// butterfly exchanges, one half of the tile at a time (the even columns, then
+// the odd ones), so a tile of 2^15 points needs the LDS of 2^14.
+//
+// The thread map is the same on both sides (pair index fastest, then row), so
+// a level whose other side is not unit-stride still reads or writes runs of
+// 64 / P consecutive rows per column and needs no LDS pass before its store.
+// The in-block stage twiddles depend on the row only and are shared by the
+// two columns of a thread.  One tile per workgroup; the XCD-aware order gives
+// each XCD a contiguous run of tiles, so neighbouring tiles meet in one L2.
+#include "fft_device.h"
+
+namespace moa {
+
+namespace {
+
+// Stage S of the two 16-point-per-thread column transforms v0 (even column)
+// and v1 (odd column); slot layout as in run_stages (LGE = 4).
+template <int LGN, int S>
+__device__ __forceinline__ void pair_stages(float2* v0, float2* v1, float2* col, int j, float sign,
+                                            const float2* twb)
+{
+    constexpr int NST = n_stages(LGN);
+    using I = StageTw<LGN, 4, S>;
+    constexpr int N = I::N, LGR = I::LGR, RS = I::RS, LGNS = I::LGNS, NS = I::NS, TPC = I::TPC, NB = I::NB;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if constexpr (NS > 1) {
+            // omega_{NS RS}^(bm r) for r < RS from the powers r = 2^b.
+            const int bm = (j + q * TPC) & (NS - 1);
+            const int e1 = bm << (kLgTwBlk - LGNS - LGR);
+            float2 pw[LGR];
+#pragma unroll
+            for (int b = 0; b < LGR; ++b) {
+                float2 w = tw_blk(twb, e1 << b);
+                w.y = -sign * w.y;  // the table holds forward roots
+                pw[b] = w;
+            }
+            float2 f[RS];
+            power_tree<LGR, true>(f, pw);
+#pragma unroll
+            for (int r = 1; r < RS; ++r) {
+                v0[q * RS + r] = cmul(v0[q * RS + r], f[r]);
+                v1[q * RS + r] = cmul(v1[q * RS + r], f[r]);
+            }
+        }
+        dft_reg<float, LGR>(v0 + q * RS, sign);
+        dft_reg<float, LGR>(v1 + q * RS, sign);
+    }
+    if constexpr (S + 1 < NST) {
+        using J = StageTw<LGN, 4, S + 1>;
+        auto put = [&](const float2* v) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int b = j + q * TPC;
+                const int base = ((b >> LGNS) << (LGNS + LGR)) + (b & (NS - 1));
+#pragma unroll
+                for (int r = 0; r < RS; ++r) col[lds_pad(base + r * NS)] = v[q * RS + r];
+            }
+        };
+        auto get = [&](float2* v) {
+#pragma unroll
+            for (int q = 0; q < J::NB; ++q)
+#pragma unroll
+                for (int r = 0; r < J::RS; ++r) v[q * J::RS + r] = col[lds_pad(j + q * TPC + r * (N / J::RS))];
+        };
+        if constexpr (S > 0) __syncthreads();  // the last exchange has been read everywhere
+        put(v0);
+        __syncthreads();
+        get(v0);
+        __syncthreads();
+        put(v1);
+        __syncthreads();
+        get(v1);
+        pair_stages<LGN, S + 1>(v0, v1, col, j, sign, twb);
+    }
+}
+
+// Byte offset helpers: every offset inside one tile is below 2^32 (the
+// planner checks the span), so per-element addresses are a uniform 64-bit
+// base plus a 32-bit lane offset.
+__device__ __forceinline__ const float2* at(const char* base, uint32_t off)
+{
+    return reinterpret_cast<const float2*>(base + size_t(off));
+}
+__device__ __forceinline__ float2* at(char* base, uint32_t off) { return reinterpret_cast<float2*>(base + size_t(off)); }
+
+}  // namespace
+
+template <int LGN, bool TIN, bool TOUT>
+__global__ void __launch_bounds__(1024) k_pass_pair(PassArgs a)
+{
+    using V = float2;
+    constexpr int E = 16;
+    constexpr int TPC = 1 << (LGN - 4);
+    static_assert(LGN >= 12 && LGN <= 14, "paired-column kernel covers 2^12 .. 2^14 points");
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    V* tl = lds + a.data_elems;  // in-block twiddles (256)
+    V* tt = tl + kTwBlkEntries;  // inter-level twiddles (256 per part)
+    const float sign = a.sign;
+    const int lgp = a.lgw - 1;   // column pairs per tile: 2^lgp
+    const int t = threadIdx.x;
+    const int u = t & ((1 << lgp) - 1);
+    const int j = t >> lgp;
+
+    // Twiddle tables first: their loads then retire ahead of the data loads
+    // (the planner keeps 256 (1 + tw_parts) <= 2048).
+    V tab[2];
+    const int nt = 256 * (1 + a.tw_parts);
+    {
+        const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
+        const V* g2 = reinterpret_cast<const V*>(a.tw_inter);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = t + 1024 * k;
+            if (i < nt) tab[k] = i < 256 ? g1[i] : g2[i - 256];
+        }
+    }
+
+    uint64_t tile = blockIdx.x;
+    if (a.xcd_remap) tile = uint64_t(blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    int64_t d0, ib, ob;
+    tile_offsets(a, tile, d0, ib, ob);
+    const char* gin = reinterpret_cast<const char*>(a.in) + ib * int64_t(sizeof(V));
+    char* gout = reinterpret_cast<char*>(a.out) + ob * int64_t(sizeof(V));
+
+    // 32-bit strides (bytes) and lane offsets; see at().
+    const uint32_t ju = uint32_t(j), uu = uint32_t(u);
+    V v0[E], v1[E];
+    {
+        const uint32_t se = uint32_t(a.in_s_e) * 8u, s0 = uint32_t(a.in_s[0]) * 8u;
+        const uint32_t step = uint32_t(TPC) * se;
+        if constexpr (TIN) {
+            const uint32_t off = 16u * uu + ju * se;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const float4 x = *reinterpret_cast<const float4*>(at(gin, off + uint32_t(m) * step));
+                v0[in_slot<LGN, 4>(m)] = make_float2(x.x, x.y);
+                v1[in_slot<LGN, 4>(m)] = make_float2(x.z, x.w);
+            }
+        } else {
+            const uint32_t o0 = 2u * uu * s0 + ju * se;
+            const uint32_t o1 = o0 + s0;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                v0[in_slot<LGN, 4>(m)] = *at(gin, o0 + uint32_t(m) * step);
+                v1[in_slot<LGN, 4>(m)] = *at(gin, o1 + uint32_t(m) * step);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = t + 1024 * k;
+        if (i < nt) tl[i] = tab[k];
+    }
+    // Stage 0 needs no twiddles; the exchange barriers publish the tables.
+    pair_stages<LGN, 0>(v0, v1, lds + u * a.col_stride, j, sign, tl);
+
+    // Inter-level factor omega^(dcol * (j + rank * TPC)): base times the
+    // powers omega^(dcol * TPC * 2^b) of the set bits b of rank.
+    if (a.tw_parts) {
+        const uint64_t mask = (uint64_t(1) << a.tw_lgroot) - 1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            V* v = c ? v1 : v0;
+            const uint64_t dcol = uint64_t(d0 + 2 * u + c);
+            V f[E];
+            f[0] = tw_inter(tt, a.tw_parts, (dcol * uint64_t(j)) & mask);
+            f[0].y = -sign * f[0].y;
+            V pw[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                pw[b] = tw_inter(tt, a.tw_parts, (dcol * (uint64_t(TPC) << b)) & mask);
+                pw[b].y = -sign * pw[b].y;
+            }
+            power_tree<4, false>(f, pw);
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = cmul(v[m], f[out_slot_rank<LGN, 4>(m)]);
+        }
+    }
+
+    const uint32_t sk = uint32_t(a.out_s_k) * 8u, s0 = uint32_t(a.out_s[0]) * 8u;
+    const uint32_t step = uint32_t(TPC) * sk;
+    if constexpr (TOUT) {
+        const uint32_t off = 16u * uu + ju * sk;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const uint32_t o = off + uint32_t(out_slot_rank<LGN, 4>(m)) * step;
+            *reinterpret_cast<float4*>(at(gout, o)) = make_float4(v0[m].x, v0[m].y, v1[m].x, v1[m].y);
+        }
+    } else {
+        const uint32_t o0 = 2u * uu * s0 + ju * sk;
+        const uint32_t o1 = o0 + s0;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const uint32_t r = uint32_t(out_slot_rank<LGN, 4>(m)) * step;
+            *at(gout, o0 + r) = v0[m];
+            *at(gout, o1 + r) = v1[m];
+        }
+    }
+}
+
+using PairFn = void (*)(PassArgs);
+
+// [lgn - 12][tin][tout]; a paired level has at least one unit-stride side.
+static const PairFn kPair[3][2][2] = {
+    {{nullptr, &k_pass_pair<12, false, true>}, {&k_pass_pair<12, true, false>, &k_pass_pair<12, true, true>}},
+    {{nullptr, &k_pass_pair<13, false, true>}, {&k_pass_pair<13, true, false>, &k_pass_pair<13, true, true>}},
+    {{nullptr, &k_pass_pair<14, false, true>}, {&k_pass_pair<14, true, false>, &k_pass_pair<14, true, true>}},
+};
+
+static PairFn pair_lookup(const PassDesc& d)
+{
+    if (d.lgn < 12 || d.lgn > 14) return nullptr;
+    return kPair[d.lgn - 12][d.in_tile_fast ? 1 : 0][d.out_tile_fast ? 1 : 0];
+}
+
+const void* pair_kernel_fn(const PassDesc& d) { return reinterpret_cast<const void*>(pair_lookup(d)); }
+
+hipError_t prepare_pair_kernel(const PassDesc& d)
+{
+    PairFn f = pair_lookup(d);
+    if (!f) return hipErrorInvalidValue;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               d.lds_bytes);
+}
+
+hipError_t launch_pair(const PassDesc& d, const PassArgs& a, hipStream_t s)
+{
+    PairFn f = pair_lookup(d);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(1024u), d.lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace moa

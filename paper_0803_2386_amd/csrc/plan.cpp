@@ -171,6 +171,47 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         return (int64_t(1) << lgw) * tpc_for(lgw);
     };
     auto threads_ok = [&](int lgw) { return threads_for(lgw) <= maxT_for(lgw); };
+    // Paired-column kernel (fft_pair.hip): a complex64 level of 2^12 .. 2^14
+    // points with a unit-stride tile side keeps a tile of 2^(15-lgn) columns
+    // in VGPRs (twice the LDS-bound width: 64-byte runs at N = 4096), moving
+    // column pairs with 16-byte accesses.  It needs even strides on every
+    // axis but digit 0 (so those accesses stay aligned), per-tile spans
+    // below 2^32 bytes (32-bit lane offsets) and at most 7 inter-level parts.
+    auto pair_ok = [&](int lgw_) {
+        if (fp64 || d.mfma || lgn < 12 || lgn > 14 || !(in_tf || out_tf)) return false;
+        if (lgw_ != 15 - lgn || lgw_ > lg0) return false;
+        if (d.tw && d.tw_parts > 7) return false;
+        const int64_t w1 = (int64_t(1) << lgw_) - 1, n1 = (int64_t(1) << lgn) - 1;
+        if (w1 * d.in_s[0] + n1 * d.in_s_e >= (int64_t(1) << 29)) return false;
+        if (w1 * d.out_s[0] + n1 * d.out_s_k >= (int64_t(1) << 29)) return false;
+        if ((in_tf && d.in_s_e % 2) || (out_tf && d.out_s_k % 2)) return false;
+        for (int i = 1; i < d.nd; ++i)
+            if ((in_tf && d.in_s[i] % 2) || (out_tf && d.out_s[i] % 2)) return false;
+        return true;
+    };
+    const int eb0 = int(elem_bytes(fp64));
+    auto finish_pair = [&](int lgw_) {
+        const int P = 1 << (lgw_ - 1);
+        d.lgw = lgw_;
+        d.lge = 4;
+        d.kmode = 3;
+        d.in_tile_fast = in_tf;
+        d.out_tile_fast = out_tf;
+        d.col_stride = moa::lds_col_stride(1 << lgn, std::max(1, 16 / P));
+        d.data_elems = P * d.col_stride;
+        d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * (d.tw ? d.tw_parts : 0)) * eb0;
+        if (d.lds_bytes > moa::kLdsBytes) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
+        d.threads = 1024;
+        int64_t blocks = d.size[0] >> lgw_;
+        for (int i = 1; i < d.nd; ++i) blocks *= d.size[i];
+        if (blocks >= (int64_t(1) << 31)) return MOA_ERR_BATCH;
+        d.blocks = blocks;
+        d.grid = blocks;  // one tile per workgroup
+        d.xcd_remap = (blocks % 8 == 0 && blocks >= 16) ? 1 : 0;
+        return MOA_OK;
+    };
+    if (want_w > 0 ? (is_pow2(want_w) && pair_ok(lg2(want_w))) : pair_ok(15 - lgn))
+        return finish_pair(want_w > 0 ? lg2(want_w) : 15 - lgn);
     int lgw = 0;
     if (want_w > 0) {
         if (!is_pow2(want_w)) return MOA_ERR_TUNING;
@@ -424,7 +465,7 @@ std::string describe_json(const moa_fft_plan_s* p)
             d.threads, (long long)d.blocks,
             d.lds_bytes, d.col_stride, d.in_tile_fast ? "true" : "false", d.out_tile_fast ? "true" : "false",
             d.xcd_remap, d.mfma == 0 ? "none" : (d.mfma == 1 ? "split_bf16" : "split_fp16"),
-            d.mfma ? 32 : (1 << lgE(d.lgn, d.lge)), d.kmode);
+            (d.mfma || d.kmode == 3) ? 32 : (1 << lgE(d.lgn, d.lge)), d.kmode);
     }
     s += "]";
     if (p->batched) {
@@ -776,11 +817,23 @@ moa_status_t moa_fft_plan_batched(moa_fft_plan_t* out, const int64_t* sizes, int
     return moa_fft_plan_batched_tuned(out, sizes, count, dtype, flags, nullptr);
 }
 
+// Paired-column levels move column pairs with 16-byte accesses on their
+// unit-stride side; a caller buffer on that side must be 16-byte aligned.
+bool pair_aligned(const PassDesc& d, const void* in, const void* out, bool reads_in, bool writes_out)
+{
+    if (d.kmode != 3) return true;
+    if (reads_in && d.in_tile_fast && (reinterpret_cast<uintptr_t>(in) & 15u)) return false;
+    if (writes_out && d.out_tile_fast && (reinterpret_cast<uintptr_t>(out) & 15u)) return false;
+    return true;
+}
+
 moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out, void* stream)
 {
     if (!valid_plan(p) || !in || !out) return MOA_ERR_NULL;
     if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
     if (p->host_only) return MOA_ERR_STATE;
+    for (size_t l = 0; l < p->passes.size(); ++l)
+        if (!pair_aligned(p->passes[l], in, out, l == 0, l + 1 == p->passes.size())) return MOA_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!(p->flags & MOA_FFT_FLAG_GRAPH)) return launch_all(p, int(dir), in, out, s);
     std::lock_guard<std::mutex> lock(p->mu);
@@ -810,6 +863,7 @@ moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t lev
     if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
     if (p->batched || level < 0 || size_t(level) >= p->passes.size()) return MOA_ERR_ARG;
     if (p->host_only) return MOA_ERR_STATE;
+    if (!pair_aligned(p->passes[size_t(level)], in, out, true, true)) return MOA_ERR_ARG;
     std::vector<moa::PassArgs> args;
     pass_args(p, int(dir), in, out, args);
     return moa::launch_pass(p->fp64, p->passes[size_t(level)], args[size_t(level)],

@@ -26,11 +26,18 @@ def pad(i):
 def check_pass(p, total, elem_bytes):
     N = p["N"]
     mfma = p["mfma"] != "none"
+    pair = p["kernel_mode"] == 3
     E = min(N, p["points_per_thread"]) if not mfma else 1
+    if pair:
+        E = 16  # per column; each thread owns two adjacent columns
     TPC = N // E
     W = p["tile_width"]
     T = p["threads"]
-    if mfma:
+    if pair:
+        assert elem_bytes == 8 and 12 <= N.bit_length() - 1 <= 14 and W * N == 1 << 15
+        assert T == 1024 == (W // 2) * TPC
+        assert p["in_tile_fast"] or p["out_tile_fast"]
+    elif mfma:
         # 32 points a thread, copied in and out over i = t + m T
         assert T * 32 == W * N and T % 64 == 0 and T <= 512
         T = W * N  # check the full (column, row) set below
@@ -75,16 +82,33 @@ def check_pass(p, total, elem_bytes):
         ib = ib + idx * axes[d]["in_stride"]
         ob = ob + idx * axes[d]["out_stride"]
     t = np.arange(T)
-    if p["in_tile_fast"]:
+    if pair:
+        # pair index fastest on both sides; columns 2u and 2u + 1
+        P = W // 2
+        u, j = t % P, t // P
+        w = np.concatenate([2 * u, 2 * u + 1])
+        j = np.concatenate([j, j])
+    elif p["in_tile_fast"]:
         w, j = t % W, t // W
     else:
         j, w = t % TPC, t // TPC
     m = np.arange(E)
     # loads: block x thread x slot
     rows = j[:, None] + m[None, :] * TPC
-    load = (ib[:, None, None] + (w * axes[0]["in_stride"])[None, :, None]
-            + rows[None, :, :] * p["dft_axis"]["in_stride"])
+    lane_in = (w * axes[0]["in_stride"])[:, None] + rows * p["dft_axis"]["in_stride"]
+    load = ib[:, None, None] + lane_in[None, :, :]
     assert load.min() >= 0 and load.max() < total
+    if pair:
+        # 32-bit lane byte offsets, and 16-byte alignment on a unit-stride side
+        lane_out = (w * axes[0]["out_stride"])[:, None] + rows * p["dft_axis"]["out_stride"]
+        assert lane_in.max() * 8 < 1 << 32 and lane_out.max() * 8 < 1 << 32
+        even = slice(0, T)
+        if p["in_tile_fast"]:
+            assert np.all(load[:, even, :] % 2 == 0)
+        if p["out_tile_fast"]:
+            st = ob[:, None, None] + lane_out[None, :, :]
+            assert np.all(st[:, even, :] % 2 == 0)
+            assert st.min() >= 0 and st.max() < total
     # stores: every (column, k) of every block
     k = np.arange(N)
     ww = np.arange(W)
@@ -95,7 +119,7 @@ def check_pass(p, total, elem_bytes):
     assert flat.size == total and np.array_equal(flat, np.arange(total)), "outputs not a permutation"
     # LDS slots
     cs = p["lds_col_stride"]
-    top = (W - 1) * cs + pad(N - 1)
+    top = ((W // 2 if pair else W) - 1) * cs + pad(N - 1)
     assert (top + 1) * elem_bytes <= p["lds_bytes"] <= 160 * 1024
 
 
@@ -109,10 +133,32 @@ def check_pass(p, total, elem_bytes):
     (1, 3, None, capi.MOA_C64), (2, 5, None, capi.MOA_C128), (64, 7, None, capi.MOA_C64),
     (1 << 14, 2, None, capi.MOA_C64), (1 << 13, 3, None, capi.MOA_C128), (1 << 15, 1, None, capi.MOA_C64),
     (1 << 18, 1, [64, 4096], capi.MOA_C64), (4096, 1, [256, 16], capi.MOA_C128),
+    (1 << 20, 2, [4096, 256], capi.MOA_C64), (1 << 16, 4, [16, 4096], capi.MOA_C64),
+    (1 << 21, 1, [8192, 256], capi.MOA_C64), (1 << 22, 1, [16384, 256], capi.MOA_C64),
+    (1 << 21, 1, [256, 8192], capi.MOA_C64),
 ])
 def test_pass_kernel_geometry(n, batch, lift, dtype):
     h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST)
     _check_plan(h, n, batch, dtype)
+
+
+@pytest.mark.parametrize("n,lift", [(1 << 24, [4096, 4096]), (1 << 21, [8192, 256]), (1 << 22, [16384, 256]),
+                                    (1 << 21, [256, 8192]), (1 << 18, [64, 4096])])
+def test_paired_columns_selected(n, lift):
+    """Complex64 levels of 2^12..2^14 points with a unit-stride tile side use
+    the paired-column kernel with 2^15 / N columns a tile; others do not."""
+    h = capi.moa_fft_plan(n, 1, lift, flags=HOST)
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    assert any(p["kernel_mode"] == 3 for p in d["passes"])
+    for p in d["passes"]:
+        big = 1 << 12 <= p["N"] <= 1 << 14
+        tf = p["batch_axes"][0]["in_stride"] == 1 or p["batch_axes"][0]["out_stride"] == 1
+        assert (p["kernel_mode"] == 3) == (big and tf)
+        if p["kernel_mode"] == 3:
+            assert p["tile_width"] * p["N"] == 1 << 15 and p["threads"] == 1024
 
 
 @pytest.mark.parametrize("prec", [capi.MOA_FFT_PREC_SPLIT_BF16, capi.MOA_FFT_PREC_SPLIT_FP16])
