@@ -126,6 +126,99 @@ __device__ __forceinline__ void power_tree(V (&f)[1 << LG], const V* pw)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Direction-specialised butterflies: FWD uses omega = exp(-2 pi i / n), the
+// adjoint its conjugate.  With the direction a template parameter the
+// factors -+i become swaps folded into the adds, and conjugated twiddles cost
+// nothing (cmul_dir flips the signs of the product instead).
+// ---------------------------------------------------------------------------
+
+// x * omega_4 = x * (-i) forward, x * (+i) adjoint.
+template <bool FWD, typename V>
+__device__ __forceinline__ V mul_w4(V x)
+{
+    return FWD ? mkc(x.y, -x.x) : mkc(-x.y, x.x);
+}
+
+// x * w (forward) or x * conj(w) (adjoint), w a forward root from a table.
+template <bool FWD, typename V>
+__device__ __forceinline__ V cmul_dir(V x, V w)
+{
+    if constexpr (FWD) return cmul(x, w);
+    else return mkc(x.x * w.x + x.y * w.y, x.y * w.x - x.x * w.y);
+}
+
+// x * omega_16^P for a constant P.
+template <bool FWD, int P, typename R, typename V>
+__device__ __forceinline__ V rot16(V x)
+{
+    constexpr int p = P & 15;
+    if constexpr (p == 0) return x;
+    else if constexpr (p == 4) return mul_w4<FWD>(x);
+    else if constexpr (p == 8) return mkc(-x.x, -x.y);
+    else if constexpr (p == 12) return mul_w4<!FWD>(x);
+    else {
+        const R c = (R)cos16(p), s = FWD ? -(R)sin16(p) : (R)sin16(p);
+        return mkc(x.x * c - x.y * s, x.x * s + x.y * c);
+    }
+}
+
+// In-place 4-point DFT, natural order in and out.
+template <bool FWD, typename V>
+__device__ __forceinline__ void dft4(V& a0, V& a1, V& a2, V& a3)
+{
+    const V t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_w4<FWD>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+// In-place 16-point DFT as 4 x 4 (n = 4 n1 + n2, k = k1 + 4 k2): 4-point
+// DFTs over n1, the factors omega_16^(n2 k1), 4-point DFTs over n2.
+template <bool FWD, typename R, typename V>
+__device__ __forceinline__ void dft16(V* v)
+{
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<FWD>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // v[4 k1 + n2] now holds Y[n2][k1].
+    v[5] = rot16<FWD, 1, R>(v[5]);
+    v[6] = rot16<FWD, 2, R>(v[6]);
+    v[7] = rot16<FWD, 3, R>(v[7]);
+    v[9] = rot16<FWD, 2, R>(v[9]);
+    v[10] = rot16<FWD, 4, R>(v[10]);
+    v[11] = rot16<FWD, 6, R>(v[11]);
+    v[13] = rot16<FWD, 3, R>(v[13]);
+    v[14] = rot16<FWD, 6, R>(v[14]);
+    v[15] = rot16<FWD, 9, R>(v[15]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<FWD>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 register grid.
+    V x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = v[4 * (k & 3) + (k >> 2)];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = x[k];
+}
+
+// In-register DFT of length 2^LGR (natural order), direction-specialised.
+template <bool FWD, typename R, int LGR, typename V>
+__device__ __forceinline__ void dft_dir(V* v)
+{
+    if constexpr (LGR == 0) {
+    } else if constexpr (LGR == 1) {
+        const V a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (LGR == 2) {
+        dft4<FWD>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (LGR == 4) {
+        dft16<FWD, R>(v);
+    } else {
+        dft_reg<R, LGR>(v, FWD ? R(-1) : R(1));
+    }
+}
+
 // Stage schedule of a length-2^lgn transform: radix-16 stages, then one stage
 // with the remaining radix.  A thread holds 2^lge points (16 or 32), i.e.
 // NB = 2^lge / radix butterflies of each stage.
@@ -166,6 +259,15 @@ __device__ __forceinline__ V tw_inter(const V* tt, int parts, uint64_t e)
 {
     V w = tt[e & 255];
     for (int p = 1; p < parts; ++p) w = cmul(w, tt[256 * p + ((e >> (8 * p)) & 255)]);
+    return w;
+}
+
+// tw_inter for exponents below 2^32.
+template <typename V>
+__device__ __forceinline__ V tw_inter32(const V* tt, int parts, uint32_t e)
+{
+    V w = tt[e & 255u];
+    for (int p = 1; p < parts; ++p) w = cmul(w, tt[256 * p + ((e >> (8 * p)) & 255u)]);
     return w;
 }
 

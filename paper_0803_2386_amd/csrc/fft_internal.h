@@ -137,9 +137,9 @@ const void* mfma_kernel_fn(const PassDesc& d);
 // Paired-column levels (fft_pair.hip): complex64, lgn in [12, 14], kmode 3.
 hipError_t launch_pair(const PassDesc& d, const PassArgs& a, hipStream_t s);
 hipError_t prepare_pair_kernel(const PassDesc& d);
-const void* pair_kernel_fn(const PassDesc& d);
+const void* pair_kernel_fn(const PassDesc& d, bool fwd);
 // The kernel function pointers, used to build HIP graph nodes.
-const void* pass_kernel_fn(bool fp64, const PassDesc& d);
+const void* pass_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
 const void* batched_kernel_fn(bool fp64);
 
 }  // namespace moa

@@ -25,10 +25,11 @@ namespace moa {
 namespace {
 
 // Stage S of the two 16-point-per-thread column transforms v0 (even column)
-// and v1 (odd column); slot layout as in run_stages (LGE = 4).
-template <int LGN, int S>
-__device__ __forceinline__ void pair_stages(float2* v0, float2* v1, float2* col, int j, float sign,
-                                            const float2* twb)
+// and v1 (odd column); slot layout as in run_stages (LGE = 4).  Every stage
+// but the last is radix 16 with one butterfly a thread (NB = 1), so each LDS
+// slot a thread touches is its padded base slot plus a constant.
+template <bool FWD, int LGN, int S>
+__device__ __forceinline__ void pair_stages(float2* v0, float2* v1, float2* col, int j, const float2* twb)
 {
     constexpr int NST = n_stages(LGN);
     using I = StageTw<LGN, 4, S>;
@@ -36,43 +37,40 @@ __device__ __forceinline__ void pair_stages(float2* v0, float2* v1, float2* col,
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         if constexpr (NS > 1) {
-            // omega_{NS RS}^(bm r) for r < RS from the powers r = 2^b.
+            // omega_{NS RS}^(bm r) for r < RS from the table powers r = 2^b.
             const int bm = (j + q * TPC) & (NS - 1);
             const int e1 = bm << (kLgTwBlk - LGNS - LGR);
             float2 pw[LGR];
 #pragma unroll
-            for (int b = 0; b < LGR; ++b) {
-                float2 w = tw_blk(twb, e1 << b);
-                w.y = -sign * w.y;  // the table holds forward roots
-                pw[b] = w;
-            }
+            for (int b = 0; b < LGR; ++b) pw[b] = tw_blk(twb, e1 << b);
             float2 f[RS];
             power_tree<LGR, true>(f, pw);
 #pragma unroll
             for (int r = 1; r < RS; ++r) {
-                v0[q * RS + r] = cmul(v0[q * RS + r], f[r]);
-                v1[q * RS + r] = cmul(v1[q * RS + r], f[r]);
+                v0[q * RS + r] = cmul_dir<FWD>(v0[q * RS + r], f[r]);
+                v1[q * RS + r] = cmul_dir<FWD>(v1[q * RS + r], f[r]);
             }
         }
-        dft_reg<float, LGR>(v0 + q * RS, sign);
-        dft_reg<float, LGR>(v1 + q * RS, sign);
+        dft_dir<FWD, float, LGR>(v0 + q * RS);
+        dft_dir<FWD, float, LGR>(v1 + q * RS);
     }
     if constexpr (S + 1 < NST) {
+        static_assert(NB == 1 && RS == 16, "inner stages are radix 16");
         using J = StageTw<LGN, 4, S + 1>;
+        // Output r of the butterfly goes to Stockham slot base + r NS.
+        const int base = ((j >> LGNS) << (LGNS + LGR)) + (j & (NS - 1));
+        float2* wp = col + lds_pad(base);
         auto put = [&](const float2* v) {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int b = j + q * TPC;
-                const int base = ((b >> LGNS) << (LGNS + LGR)) + (b & (NS - 1));
-#pragma unroll
-                for (int r = 0; r < RS; ++r) col[lds_pad(base + r * NS)] = v[q * RS + r];
-            }
+            for (int r = 0; r < RS; ++r) wp[NS == 1 ? r : lds_pad(r * NS)] = v[r];
         };
+        // Input r of butterfly q of the next stage is row j + q TPC + r N / RS'.
+        float2* rp = col + lds_pad(j);
         auto get = [&](float2* v) {
 #pragma unroll
             for (int q = 0; q < J::NB; ++q)
 #pragma unroll
-                for (int r = 0; r < J::RS; ++r) v[q * J::RS + r] = col[lds_pad(j + q * TPC + r * (N / J::RS))];
+                for (int r = 0; r < J::RS; ++r) v[q * J::RS + r] = rp[lds_pad(q * TPC + r * (N / J::RS))];
         };
         if constexpr (S > 0) __syncthreads();  // the last exchange has been read everywhere
         put(v0);
@@ -82,7 +80,7 @@ __device__ __forceinline__ void pair_stages(float2* v0, float2* v1, float2* col,
         put(v1);
         __syncthreads();
         get(v1);
-        pair_stages<LGN, S + 1>(v0, v1, col, j, sign, twb);
+        pair_stages<FWD, LGN, S + 1>(v0, v1, col, j, twb);
     }
 }
 
@@ -97,8 +95,9 @@ __device__ __forceinline__ float2* at(char* base, uint32_t off) { return reinter
 
 }  // namespace
 
-template <int LGN, bool TIN, bool TOUT>
-__global__ void __launch_bounds__(1024) k_pass_pair(PassArgs a)
+// One tile of a paired-column level (the whole kernel body; 1024 threads).
+template <int LGN, bool TIN, bool TOUT, bool FWD>
+__device__ __forceinline__ void pair_tile(const PassArgs& a, uint64_t tile)
 {
     using V = float2;
     constexpr int E = 16;
@@ -109,7 +108,6 @@ __global__ void __launch_bounds__(1024) k_pass_pair(PassArgs a)
     V* lds = reinterpret_cast<V*>(smem_raw);
     V* tl = lds + a.data_elems;  // in-block twiddles (256)
     V* tt = tl + kTwBlkEntries;  // inter-level twiddles (256 per part)
-    const float sign = a.sign;
     const int lgp = a.lgw - 1;   // column pairs per tile: 2^lgp
     const int t = threadIdx.x;
     const int u = t & ((1 << lgp) - 1);
@@ -129,8 +127,6 @@ __global__ void __launch_bounds__(1024) k_pass_pair(PassArgs a)
         }
     }
 
-    uint64_t tile = blockIdx.x;
-    if (a.xcd_remap) tile = uint64_t(blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
     int64_t d0, ib, ob;
     tile_offsets(a, tile, d0, ib, ob);
     const char* gin = reinterpret_cast<const char*>(a.in) + ib * int64_t(sizeof(V));
@@ -166,28 +162,25 @@ __global__ void __launch_bounds__(1024) k_pass_pair(PassArgs a)
         if (i < nt) tl[i] = tab[k];
     }
     // Stage 0 needs no twiddles; the exchange barriers publish the tables.
-    pair_stages<LGN, 0>(v0, v1, lds + u * a.col_stride, j, sign, tl);
+    pair_stages<FWD, LGN, 0>(v0, v1, lds + u * a.col_stride, j, tl);
 
     // Inter-level factor omega^(dcol * (j + rank * TPC)): base times the
-    // powers omega^(dcol * TPC * 2^b) of the set bits b of rank.
+    // powers omega^(dcol * TPC * 2^b) of the set bits b of rank.  The root
+    // is at most 2^32 (planner), so exponents wrap in 32-bit arithmetic.
     if (a.tw_parts) {
-        const uint64_t mask = (uint64_t(1) << a.tw_lgroot) - 1;
+        const uint32_t mask = uint32_t((uint64_t(1) << a.tw_lgroot) - 1);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             V* v = c ? v1 : v0;
-            const uint64_t dcol = uint64_t(d0 + 2 * u + c);
+            const uint32_t dcol = uint32_t(d0) + 2u * uu + uint32_t(c);
             V f[E];
-            f[0] = tw_inter(tt, a.tw_parts, (dcol * uint64_t(j)) & mask);
-            f[0].y = -sign * f[0].y;
+            f[0] = tw_inter32(tt, a.tw_parts, (dcol * ju) & mask);
             V pw[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                pw[b] = tw_inter(tt, a.tw_parts, (dcol * (uint64_t(TPC) << b)) & mask);
-                pw[b].y = -sign * pw[b].y;
-            }
+            for (int b = 0; b < 4; ++b) pw[b] = tw_inter32(tt, a.tw_parts, (dcol * (uint32_t(TPC) << b)) & mask);
             power_tree<4, false>(f, pw);
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[m] = cmul(v[m], f[out_slot_rank<LGN, 4>(m)]);
+            for (int m = 0; m < E; ++m) v[m] = cmul_dir<FWD>(v[m], f[out_slot_rank<LGN, 4>(m)]);
         }
     }
 
@@ -212,34 +205,50 @@ __global__ void __launch_bounds__(1024) k_pass_pair(PassArgs a)
     }
 }
 
-using PairFn = void (*)(PassArgs);
-
-// [lgn - 12][tin][tout]; a paired level has at least one unit-stride side.
-static const PairFn kPair[3][2][2] = {
-    {{nullptr, &k_pass_pair<12, false, true>}, {&k_pass_pair<12, true, false>, &k_pass_pair<12, true, true>}},
-    {{nullptr, &k_pass_pair<13, false, true>}, {&k_pass_pair<13, true, false>, &k_pass_pair<13, true, true>}},
-    {{nullptr, &k_pass_pair<14, false, true>}, {&k_pass_pair<14, true, false>, &k_pass_pair<14, true, true>}},
-};
-
-static PairFn pair_lookup(const PassDesc& d)
+template <int LGN, bool TIN, bool TOUT, bool FWD>
+__global__ void __launch_bounds__(1024) k_pass_pair(PassArgs a)
 {
-    if (d.lgn < 12 || d.lgn > 14) return nullptr;
-    return kPair[d.lgn - 12][d.in_tile_fast ? 1 : 0][d.out_tile_fast ? 1 : 0];
+    uint64_t tile = blockIdx.x;
+    if (a.xcd_remap) tile = uint64_t(blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    pair_tile<LGN, TIN, TOUT, FWD>(a, tile);
 }
 
-const void* pair_kernel_fn(const PassDesc& d) { return reinterpret_cast<const void*>(pair_lookup(d)); }
+using PairFn = void (*)(PassArgs);
+
+#define MOA_PAIR_ROW(L, F)                                                                              \
+    {                                                                                                   \
+        {nullptr, &k_pass_pair<L, false, true, F>}, { &k_pass_pair<L, true, false, F>, &k_pass_pair<L, true, true, F> } \
+    }
+
+// [direction][lgn - 12][tin][tout]; a paired level has at least one unit-stride side.
+static const PairFn kPair[2][3][2][2] = {
+    {MOA_PAIR_ROW(12, true), MOA_PAIR_ROW(13, true), MOA_PAIR_ROW(14, true)},
+    {MOA_PAIR_ROW(12, false), MOA_PAIR_ROW(13, false), MOA_PAIR_ROW(14, false)},
+};
+
+static PairFn pair_lookup(const PassDesc& d, bool fwd)
+{
+    if (d.lgn < 12 || d.lgn > 14) return nullptr;
+    return kPair[fwd ? 0 : 1][d.lgn - 12][d.in_tile_fast ? 1 : 0][d.out_tile_fast ? 1 : 0];
+}
+
+const void* pair_kernel_fn(const PassDesc& d, bool fwd) { return reinterpret_cast<const void*>(pair_lookup(d, fwd)); }
 
 hipError_t prepare_pair_kernel(const PassDesc& d)
 {
-    PairFn f = pair_lookup(d);
-    if (!f) return hipErrorInvalidValue;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               d.lds_bytes);
+    for (bool fwd : {true, false}) {
+        PairFn f = pair_lookup(d, fwd);
+        if (!f) return hipErrorInvalidValue;
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_pair(const PassDesc& d, const PassArgs& a, hipStream_t s)
 {
-    PairFn f = pair_lookup(d);
+    PairFn f = pair_lookup(d, a.sign < 0.f);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(1024u), d.lds_bytes, s, a);
     return hipGetLastError();

@@ -176,11 +176,12 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     // in VGPRs (twice the LDS-bound width: 64-byte runs at N = 4096), moving
     // column pairs with 16-byte accesses.  It needs even strides on every
     // axis but digit 0 (so those accesses stay aligned), per-tile spans
-    // below 2^32 bytes (32-bit lane offsets) and at most 7 inter-level parts.
+    // below 2^32 bytes (32-bit lane offsets), at most 7 inter-level parts and
+    // an inter-level root of at most 2^32 (32-bit exponents).
     auto pair_ok = [&](int lgw_) {
         if (fp64 || d.mfma || lgn < 12 || lgn > 14 || !(in_tf || out_tf)) return false;
         if (lgw_ != 15 - lgn || lgw_ > lg0) return false;
-        if (d.tw && d.tw_parts > 7) return false;
+        if (d.tw && (d.tw_parts > 7 || d.tw_lgroot > 32)) return false;
         const int64_t w1 = (int64_t(1) << lgw_) - 1, n1 = (int64_t(1) << lgn) - 1;
         if (w1 * d.in_s[0] + n1 * d.in_s_e >= (int64_t(1) << 29)) return false;
         if (w1 * d.out_s[0] + n1 * d.out_s_k >= (int64_t(1) << 29)) return false;
@@ -608,7 +609,7 @@ moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, G
         pass_args(p, dir, in, out, args);
         for (size_t l = 0; l < p->passes.size() && st == MOA_OK; ++l) {
             const PassDesc& d = p->passes[l];
-            st = add_node(g.graph, &prev, moa::pass_kernel_fn(p->fp64, d), dim3(unsigned(d.grid)),
+            st = add_node(g.graph, &prev, moa::pass_kernel_fn(p->fp64, d, dir == MOA_FFT_FORWARD), dim3(unsigned(d.grid)),
                           dim3(unsigned(d.threads)), d.lds_bytes, &args[l]);
         }
     }
