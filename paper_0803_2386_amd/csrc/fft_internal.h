@@ -8,15 +8,13 @@
 namespace moa {
 
 constexpr int kMaxDigits = 8;     // batch digits of one pass descriptor
-constexpr int kMaxThreads = 512;  // workgroup size limit (1024 for the large staged-store level kernel)
+constexpr int kMaxThreads = 512;  // level-kernel workgroup limit (1024: staged-store, paired-column and batch kernels)
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kMaxLgBlockC64 = 14;  // 2^14 complex64 = 128 KiB (+pad) in LDS
 constexpr int kMaxLgBlockC128 = 13; // 2^13 complex128
 
 // Entries of the in-block twiddle table kept in LDS (two halves of 128).
 constexpr int kTwBlkEntries = 256;
-// Most transforms one task of the uneven batch holds (one per thread).
-constexpr int kMaxTaskCols = 512;
 
 // Elements each thread keeps in registers across a pass (the radix of the
 // register-resident stages) is 2^lge, lge = 4 or 5; a transform shorter than
@@ -119,7 +117,7 @@ struct BatchArgs {
     const void* tw_blk;
     int ntasks;
     int task0;                    // first task of this launch
-    int data_elems;               // LDS elements of the data tile (tables follow)
+    int data_elems;               // LDS elements of the exchange tile (the twiddle table follows)
     float sign;
 };
 

@@ -628,7 +628,10 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
 {
     const int maxlg = max_lg_block(p->fp64);
     const size_t eb = elem_bytes(p->fp64);
-    const int T = max_threads(p->fp64);
+    // Tasks of up to 2^13 points on 512 threads, 16 points a thread (one
+    // transform a thread when it is shorter than that), or one complex64
+    // transform of 2^14 points, 32 points a thread.
+    const int T = 512;
     const int64_t count = int64_t(p->sizes.size());
     std::vector<int64_t> off(size_t(count) + 1, 0);
     std::vector<std::vector<int64_t>> by_lg(size_t(maxlg) + 1);
@@ -646,12 +649,11 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     for (int lg = maxlg; lg >= 0; --lg) {
         const auto& idx = by_lg[size_t(lg)];
         if (idx.empty()) continue;
-        const int tpc = 1 << (lg - lgE(lg, lg >= 14 ? 5 : 4));
+        const int lge = (!p->fp64 && lg == 14) ? 5 : 4;
+        const int tpc = 1 << (lg - lgE(lg, lge));
         const int cs = moa::lds_col_stride(1 << lg, tpc);
-        // LDS of one full tile: 2^14 complex64 or 2^13 complex128 points.
-        const int64_t budget = int64_t(moa::lds_padded_len(1 << maxlg)) * int64_t(eb);
-        int per = std::min(T / tpc, int(budget / (int64_t(cs) * int64_t(eb))));
-        per = std::max(per, 1);
+        const int per = T / tpc;  // 2^(13 - lg) transforms of 16 points or more, T shorter ones
+        const bool uses_lds = lg > 4;  // a single register stage needs no exchange
         const int first_task = int(p->tasks.size());
         for (size_t k = 0; k < idx.size(); k += size_t(per)) {
             const int cnt = int(std::min<size_t>(size_t(per), idx.size() - k));
@@ -661,15 +663,16 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
             tk.first = int64_t(p->toff.size());
             for (int w = 0; w < cnt; ++w) p->toff.push_back(off[size_t(idx[k + size_t(w)])]);
             p->tasks.push_back(tk);
-            lds_max = std::max(lds_max, int(int64_t(cnt) * cs * int64_t(eb)));
+            if (uses_lds) lds_max = std::max(lds_max, int(int64_t(cnt) * cs * int64_t(eb)));
         }
         p->size_ranges.push_back({first_task, int(p->tasks.size()) - first_task});
     }
     // Within a size the full tasks come first; sizes are already longest first.
     p->batch_threads = T;
-    // LDS: data tile, in-block twiddle table, two task-offset buffers.
+    // LDS: exchange tile, then the in-block twiddle table.
     p->batch_data_elems = int(lds_max / int64_t(eb));
-    p->batch_lds = lds_max + moa::kTwBlkEntries * int(eb) + 2 * moa::kMaxTaskCols * int(sizeof(int64_t));
+    p->batch_lds = lds_max + moa::kTwBlkEntries * int(eb);
+    if (p->batch_lds > moa::kLdsBytes) return MOA_ERR_STATE;
     int grid = int(p->tasks.size());
     if (tuning && tuning->persistent_blocks < 0) return MOA_ERR_TUNING;
     if (tuning && tuning->persistent_blocks > 0) {
