@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X dimension-lifted FFT.
 
-Default workload: one complex64 transform of n = 2^24 points through the lift
+Headline workload: one complex64 transform of n = 2^24 points through the lift
 <4096 4096> (two HBM passes: column FFTs with the inter-level twiddle and the
 reshape-transpose folded into the store, then row FFTs with the final
 transpose folded into the store).  A step is one full transform; inputs are
@@ -10,17 +10,25 @@ resident in HBM before the timed region.  Prints one JSON line.
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
 
 Throughput is 5 n log2(n) / t (GFLOP/s).  The roofline block reports the
-dominant kernel (the slower of the two level launches) against the 8 TB/s
-HBM peak with its algorithmic bytes (read + write of every element once per
-launch), timed with HIP events on the stream the kernels run on.
+dominant kernel (the slower of the two level launches, each timed in its place
+in the x -> workspace -> out chain with HIP events on the launch stream)
+against the 8 TB/s HBM peak with its algorithmic bytes (read + write of every
+element once per launch); `traffic` is the HBM bytes per launch that the
+rocprofv3 FETCH_SIZE / WRITE_SIZE counters measured for the same kernel
+source (profiles/traffic.json), or null when the kernel source has changed
+since.  The extras time the other workloads (uneven batch, forward+adjoint,
+split-precision matrix-core levels, the tuned lift, complex128 latency); the
+CPU leg times the FP64 oracle and states the error of every result against it.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +37,8 @@ if ROOT not in sys.path:
 
 METRIC = "FFT GFLOP/s (5n·log2n/t) & HBM GB/s vs peak, batched/MFMA vs plain, at stated error"
 HBM_PEAK_GBS = 8000.0
+MFMA_DENSE_PEAK_TFLOPS = 2500.0  # bf16 / fp16 dense matrix-core peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def gflops(n, batch, seconds):
@@ -45,17 +55,6 @@ def time_events(fn, reps, torch):
     e.record()
     e.synchronize()
     return s.elapsed_time(e) / reps
-
-
-def kernel_name(p):
-    """Device symbol (demangled) of the kernel a pass descriptor launches."""
-    lg = int(math.log2(p["N"]))
-    tin, tout = str(p["in_tile_fast"]).lower(), str(p["out_tile_fast"]).lower()
-    if p["mfma"] != "none":
-        return "k_pass_mfma<%d, %d>" % (lg, 1 if p["mfma"] == "split_bf16" else 2)
-    if p["kernel_mode"] == 3:
-        return "k_pass_pair<%d, %s, %s>" % (lg, tin, tout)
-    return "k_pass<float, %d, %d, %s, %s>" % (lg, p["kernel_mode"], tin, tout)
 
 
 def level_times_in_chain(plan, x, out, reps, torch):
@@ -80,42 +79,58 @@ def level_times_in_chain(plan, x, out, reps, torch):
     return [sum(ev[r][lvl].elapsed_time(ev[r][lvl + 1]) for r in range(reps)) / reps for lvl in range(levels)]
 
 
-def rel_err(got, want, np):
-    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+def kernel_name(p):
+    """Device symbol (demangled, without the direction argument) of the
+    kernel a pass descriptor launches."""
+    lg = int(math.log2(p["N"]))
+    tin, tout = str(p["in_tile_fast"]).lower(), str(p["out_tile_fast"]).lower()
+    if p["mfma"] != "none":
+        return "k_pass_mfma<%d, %d>" % (lg, 1 if p["mfma"] == "split_bf16" else 2)
+    if p["kernel_mode"] == 3:
+        return "k_pass_pair<%d, %s, %s>" % (lg, tin, tout)
+    return "k_pass<float, %d, %d, %s, %s>" % (lg, p["kernel_mode"], tin, tout)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--copy-ref", action="store_true",
-                    help="also run a plain device copy of the same buffer (reference for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(a sharded transform would need an all-to-all exchange between GPUs).", file=sys.stderr)
-        sys.exit(2)
+def sources_digest(paths):
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
-    import numpy as np
-    import torch
 
-    from paper_0803_2386_amd import fft as mfft
-    from paper_0803_2386_amd import inputs
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter runs of `kernel`, if
+    its sources are unchanged since they were taken, else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            entry = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not entry:
+        return None
+    try:
+        if sources_digest(entry["sources"]) != entry["sources_sha256"]:
+            return None
+    except OSError:
+        return None
+    return int(entry["hbm_bytes_per_launch"])
 
+
+def rel_err_rows(got, want, np):
+    got = np.atleast_2d(got)
+    want = np.atleast_2d(want)
+    return float((np.linalg.norm(got - want, axis=-1) / np.linalg.norm(want, axis=-1)).max())
+
+
+def headline(args, torch, np, mfft, inputs):
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     n, batch, lift = 1 << 24, 1, [4096, 4096]
     x_np = inputs.uniform_complex(n, seed=args.seed, dtype=np.complex64)
     x = torch.from_numpy(x_np).to(dev)
     out = torch.empty_like(x)
     plan = mfft.Plan(n, batch, lift, dtype=torch.complex64)
     print(f"[bench] workload c64 n=2^24 lift {lift}; warmup {args.warmup}", file=sys.stderr, flush=True)
-
     for _ in range(args.warmup):
         plan.forward(x, out=out)
     torch.cuda.synchronize()
@@ -128,29 +143,24 @@ def main():
     value = gflops(n, batch, ms_per_step / 1e3)
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.1f} GFLOP/s",
           file=sys.stderr, flush=True)
-
     if args.copy_ref:
         ref = torch.empty_like(x)
         copy_ms = time_events(lambda: ref.copy_(x), args.steps, torch)
         print(f"[bench] reference copy of {8 * n} B: {copy_ms:.4f} ms", file=sys.stderr, flush=True)
 
-    # Per-level kernel durations, each level in its place in the chain
-    # x -> workspace -> ... -> out (so the cache state matches the full
-    # transform), timed by HIP events on the launch stream.
-    levels = plan.num_levels
     level_ms = level_times_in_chain(plan, x, out, args.steps, torch)
     step_event_ms = time_events(lambda: plan.forward(x, out=out), args.steps, torch)
     dom = int(np.argmax(level_ms))
     bytes_per_launch = 2 * 8 * n * batch  # read + write every element once
     achieved = bytes_per_launch / (level_ms[dom] * 1e-3) / 1e9
     desc = plan.describe()
-    kernel_names = [kernel_name(p) for p in desc["passes"]]
+    names = [kernel_name(p) for p in desc["passes"]]
+    traffic = measured_traffic(names[dom])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kernel_names[dom], "level": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": names[dom], "level": dom, "level_kernels": names,
                 "level_ms": [round(v, 5) for v in level_ms],
                 "algorithmic_bytes_per_launch": bytes_per_launch}
-
     result = {"metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1,
               "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -159,40 +169,28 @@ def main():
               "roofline": roofline,
               "hbm_gbs_step": round(2 * bytes_per_launch / (ms_per_step * 1e-3) / 1e9, 1),
               "event_ms_per_step": round(step_event_ms, 5)}
-
-    if not args.no_parity or not args.no_cpu_baseline:
-        import oracle
-        y = out.cpu().numpy().astype(np.complex128)
-        xin = x_np.astype(np.complex128)
-        t2 = time.perf_counter()
-        want = oracle.fft(xin)
-        t3 = time.perf_counter()
-        err = rel_err(y, want, np)
-        result["error_vs_fp64_oracle"] = {"rel_l2": err, "tolerance": 2e-6 * 24, "pass": err <= 2e-6 * 24}
-        if not args.no_cpu_baseline:
-            result["cpu_baseline"] = {"value": round(gflops(n, 1, t3 - t2), 3), "unit": "GFLOP/s", "cores": 1,
-                                      "kind": "oracle",
-                                      "sample": "one full n=2^24 transform of the same input (FP64 Van Loan "
-                                                "radix-2, single thread), %.2f s" % (t3 - t2)}
-
-    if not args.no_extras:
-        result["extras"] = extras(args, torch, np, mfft, inputs)
-
-    print(json.dumps(result), flush=True)
+    sample = {"x": x_np, "y": out.cpu().numpy()}
+    plan.close()
+    return result, sample
 
 
 def extras(args, torch, np, mfft, inputs):
-    """Other workloads, timed the same way (context for the headline line)."""
-    ex = {}
+    """Other workloads, timed the same way (context for the headline line).
+    Returns the records and, per record, host copies of a few transforms for
+    the error statement of the CPU leg."""
+    ex, samples = {}, {}
     dev = torch.device("cuda", 0)
     reps = max(5, args.steps // 2)
+
     # Uneven batch: one persistent launch vs one plain launch per size.
     sizes = [int(s) for s in inputs.uneven_sizes(8192, 6, 14, seed=args.seed)]
     total = sum(sizes)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
     flops = sum(5.0 * s * math.log2(s) for s in sizes)
     xb = inputs.device_uniform_complex(total, args.seed, torch.complex64, dev)
     ob = torch.empty_like(xb)
     rec = {"transforms": len(sizes), "elements": total}
+    pick = [0, int(np.argmax(sizes)), len(sizes) - 1]
     for name, kw in (("persistent", {}), ("per_size", {"per_size": True}),
                      ("persistent_graph", {"graph": True})):
         p = mfft.BatchedPlan(sizes, **kw)
@@ -200,9 +198,17 @@ def extras(args, torch, np, mfft, inputs):
             p.forward(xb, out=ob)
         ms = time_events(lambda: p.forward(xb, out=ob), reps, torch)
         rec[name] = {"ms": round(ms, 5), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
-                     "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1)}
+                     "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm_peak": round(16 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if name == "persistent_graph":
+            xs, ys = xb.cpu().numpy(), ob.cpu().numpy()
+            samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
+                                       for i in pick]
         p.close()
+    rec["persistent_vs_per_size"] = round(rec["per_size"]["ms"] / rec["persistent"]["ms"], 3)
     ex["uneven_batch_8192_2^6..2^14"] = rec
+    del xb, ob
+
     # Differentiable workload: forward + adjoint, 256 x 2^16, lift <256 256>.
     n, B = 1 << 16, 256
     p = mfft.Plan(n, B, [256, 256])
@@ -218,6 +224,48 @@ def extras(args, torch, np, mfft, inputs):
     ex["fwd_adj_b256_2^16"] = {"ms": round(ms, 5), "gflops": round(2 * gflops(n, B, ms * 1e-3), 1),
                                "hbm_gbs": round(4 * 16 * n * B / (ms * 1e-3) / 1e9, 1)}
     p.close()
+    del xa, ya, za
+
+    # Split-precision matrix-core levels vs FP32, 256 x 2^20, lift <256 4096>.
+    n, B, lift = 1 << 20, 256, [256, 4096]
+    xm = inputs.device_uniform_complex(n * B, args.seed + 3, torch.complex64, dev)
+    ym = torch.empty_like(xm)
+    rows = [0, B - 1]
+    xs = xm.view(B, n)[rows].cpu().numpy()
+    rec = {"lift": lift}
+    for prec in ("native", "split_bf16", "split_fp16"):
+        p = mfft.Plan(n, B, lift, prec=prec)
+        d = p.describe()
+        p.forward(xm, out=ym)
+        mreps = max(3, reps // 2)
+        ms = time_events(lambda: p.forward(xm, out=ym), mreps, torch)
+        lv = level_times_in_chain(p, xm, ym, mreps, torch)
+        levels = len(d["passes"])
+        r = {"ms": round(ms, 4), "gflops": round(gflops(n, B, ms * 1e-3), 1),
+             "hbm_gbs": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9, 1),
+             "level_ms": [round(v, 4) for v in lv], "kernels": [kernel_name(q) for q in d["passes"]]}
+        stages = sum(int(math.log2(q["N"])) // 4 for q in d["passes"] if q["mfma"] != "none")
+        if stages:
+            # 6 MFMA 16x16x32 per 16 butterflies of a stage: 384 flops a point.
+            tf = 384.0 * stages * n * B / (ms * 1e-3) / 1e12
+            r["mfma_stages"] = stages
+            r["mfma_tflops"] = round(tf, 1)
+            r["mfma_frac_dense_peak"] = round(tf / MFMA_DENSE_PEAK_TFLOPS, 4)
+        bound = 2e-6 * math.log2(n) if prec != "split_bf16" else 2.0 * stages * 2.0 ** -16
+        samples["mfma_" + prec] = [(xs[i], ym.view(B, n)[rows[i]].cpu().numpy(), bound) for i in range(len(rows))]
+        rec[prec] = r
+        p.close()
+    ex["split_mfma_b256_2^20"] = rec
+    del xm, ym
+
+    # The autotuner's lift and tile widths for n = 2^24 (up to three levels).
+    from paper_0803_2386_amd import tune
+    with tempfile.TemporaryDirectory() as td:
+        os.environ["MOA_FFT_TUNE_CACHE"] = os.path.join(td, "tune.json")
+        best = tune.tune(1 << 24, 1, max_levels=3, reps=5, use_cache=False)
+    ex["tuned_2^24"] = {"lift": best["lift"], "tuning": best["tuning"], "ms": round(best["ms"], 5),
+                        "gflops": round(gflops(1 << 24, 1, best["ms"] * 1e-3), 1), "candidates": best["tried"]}
+
     # Latency of the complex128 n = 2^10 transform (single workgroup).
     p = mfft.Plan(1 << 10, 1, None, dtype=torch.complex128)
     xc = inputs.device_uniform_complex(1 << 10, args.seed + 2, torch.complex128, dev)
@@ -225,8 +273,71 @@ def extras(args, torch, np, mfft, inputs):
     for _ in range(10):
         p.forward(xc, out=yc)
     ex["c128_n1024_us_per_call"] = round(1e3 * time_events(lambda: p.forward(xc, out=yc), 200, torch), 3)
+    samples["c128_n1024"] = [(xc.cpu().numpy(), yc.cpu().numpy(), 1e-13)]
     p.close()
-    return ex
+    return ex, samples
+
+
+def cpu_baseline_leg(args, np, result, sample, samples):
+    """Time the FP64 oracle on the host (one full headline transform, one
+    thread) and state the error of every GPU result against it."""
+    import oracle
+    xin = sample["x"].astype(np.complex128)
+    t0 = time.perf_counter()
+    want = oracle.fft(xin)
+    t1 = time.perf_counter()
+    err = rel_err_rows(sample["y"].astype(np.complex128), want, np)
+    n = xin.size
+    result["error_vs_fp64_oracle"] = {"rel_l2": err, "tolerance": 2e-6 * math.log2(n),
+                                      "pass": err <= 2e-6 * math.log2(n)}
+    result["cpu_baseline"] = {"value": round(gflops(n, 1, t1 - t0), 3), "unit": "GFLOP/s", "cores": 1,
+                              "kind": "oracle",
+                              "sample": "one full n=2^24 transform of the headline input (FP64 Van Loan radix-2, "
+                                        "single thread), %.2f s" % (t1 - t0)}
+    ex = result.get("extras")
+    if not ex:
+        return
+    errs = {}
+    for name, cases in samples.items():
+        worst, ok = 0.0, True
+        for xs, ys, tol in cases:
+            e = rel_err_rows(ys.astype(np.complex128), oracle.fft(xs.astype(np.complex128)), np)
+            worst = max(worst, e)
+            ok = ok and e <= tol
+        errs[name] = {"rel_l2_max": worst, "transforms": len(cases), "tolerance": cases[0][2], "pass": ok}
+    ex["error_vs_fp64_oracle"] = errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error statement)")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run a plain device copy of the same buffer (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(a sharded transform would need an all-to-all exchange between GPUs).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0803_2386_amd import fft as mfft
+    from paper_0803_2386_amd import inputs
+
+    torch.cuda.set_device(torch.device("cuda", 0))
+    result, sample = headline(args, torch, np, mfft, inputs)
+    samples = {}
+    if not args.no_extras:
+        result["extras"], samples = extras(args, torch, np, mfft, inputs)
+    if not args.no_cpu_baseline:
+        cpu_baseline_leg(args, np, result, sample, samples)
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":

@@ -111,9 +111,13 @@ def _time_plan(torch, plan, x, out, reps: int) -> float:
 
 
 def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: int = 3, reps: int = 10,
-         candidates_limit: Optional[int] = None, use_cache: bool = True, verbose: bool = False) -> dict:
+         candidates_limit: Optional[int] = None, use_cache: bool = True, verbose: bool = False,
+         refine: int = 5) -> dict:
     """Time the candidate lifts/tile widths for (n, batch) on the current
-    device; returns {"lift", "tuning", "ms", "tried"} and caches it."""
+    device; returns {"lift", "tuning", "ms", "tried"} and caches it.
+
+    Two rounds: every lift with the planner's default tile widths, then every
+    tile width for the `refine` fastest lifts."""
     import torch
 
     from . import fft as mfft
@@ -128,24 +132,30 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
             hit = _load_cache().get(key)
         if hit:
             return hit
-    cands = candidates(n, batch, dcode, pcode, max_levels)
-    if candidates_limit:
-        cands = cands[:candidates_limit]
     real = torch.float32 if dtype == torch.complex64 else torch.float64
     x = torch.zeros(2 * n * batch, dtype=real, device=dev).view(dtype)
     out = torch.empty_like(x)
-    best = None
-    tried = 0
-    for lift, tuning in cands:
-        plan = mfft.Plan(n, batch, lift, dtype=dtype, prec=prec, tuning=tuning)
-        ms = _time_plan(torch, plan, x, out, reps)
-        plan.close()
-        tried += 1
-        if verbose:
-            print(f"tune n={n} batch={batch} lift={lift} tuning={tuning}: {ms:.4f} ms", flush=True)
-        if best is None or ms < best["ms"]:
-            best = {"lift": lift, "tuning": tuning, "ms": ms}
-    best["tried"] = tried
+    timed = []
+
+    def run(cands):
+        for lift, tuning in cands:
+            if candidates_limit and len(timed) >= candidates_limit:
+                return
+            plan = mfft.Plan(n, batch, lift, dtype=dtype, prec=prec, tuning=tuning)
+            ms = _time_plan(torch, plan, x, out, reps)
+            plan.close()
+            timed.append({"lift": list(lift), "tuning": tuning, "ms": ms})
+            if verbose:
+                print(f"tune n={n} batch={batch} lift={lift} tuning={tuning}: {ms:.4f} ms", flush=True)
+
+    run([(lift, None) for lift in lift_candidates(n, dcode, max_levels)
+         if _plan_ok(n, batch, lift, dcode, pcode, None) is not None])
+    top = sorted(timed, key=lambda r: r["ms"])[:max(1, refine)]
+    for r in top:
+        run([c for c in candidates(n, batch, dcode, pcode, max_levels=len(r["lift"]))
+             if c[0] == r["lift"] and c[1] is not None])
+    best = dict(min(timed, key=lambda r: r["ms"]))
+    best["tried"] = len(timed)
     if use_cache:
         with _lock:
             c = _load_cache()
