@@ -85,7 +85,10 @@ def kernel_name(p):
     lg = int(math.log2(p["N"]))
     tin, tout = str(p["in_tile_fast"]).lower(), str(p["out_tile_fast"]).lower()
     if p["mfma"] != "none":
-        return "k_pass_mfma<%d, %d>" % (lg, 1 if p["mfma"] == "split_bf16" else 2)
+        prec = 1 if p["mfma"] == "split_bf16" else 2
+        if p["kernel_mode"] == 3:
+            return "k_pass_mfma_pair<%d, %d, %s, %s>" % (lg, prec, tin, tout)
+        return "k_pass_mfma<%d, %d>" % (lg, prec)
     if p["kernel_mode"] == 3:
         return "k_pass_pair<%d, %s, %s>" % (lg, tin, tout)
     return "k_pass<float, %d, %d, %s, %s>" % (lg, p["kernel_mode"], tin, tout)

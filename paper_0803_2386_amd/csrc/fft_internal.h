@@ -131,7 +131,7 @@ hipError_t prepare_batched_kernel(bool fp64, int lds_bytes);
 // Matrix-core levels (fft_mfma.hip): lgn in {4, 8, 12}, d.mfma = 1 (bf16) or 2 (fp16).
 hipError_t launch_mfma(const PassDesc& d, const PassArgs& a, hipStream_t s);
 hipError_t prepare_mfma_kernel(const PassDesc& d);
-const void* mfma_kernel_fn(const PassDesc& d);
+const void* mfma_kernel_fn(const PassDesc& d, bool fwd);
 // Paired-column levels (fft_pair.hip): complex64, lgn in [12, 14], kmode 3.
 hipError_t launch_pair(const PassDesc& d, const PassArgs& a, hipStream_t s);
 hipError_t prepare_pair_kernel(const PassDesc& d);

@@ -236,7 +236,7 @@ static PassFn pass_fn_lookup(bool fp64, int lgn, int km, bool tin, bool tout)
 
 const void* pass_kernel_fn(bool fp64, const PassDesc& d, bool fwd)
 {
-    if (d.mfma) return mfma_kernel_fn(d);
+    if (d.mfma) return mfma_kernel_fn(d, fwd);
     if (d.kmode == 3) return pair_kernel_fn(d, fwd);
     return reinterpret_cast<const void*>(pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast));
 }

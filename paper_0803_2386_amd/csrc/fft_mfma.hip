@@ -253,6 +253,278 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Paired-column matrix-core level (LGN = 8 or 12).  The tile is the one of
+// the paired-column FP32 kernel -- 2^(15 - LGN) columns, each thread two
+// adjacent columns moved with 16-byte accesses on a unit-stride side -- so
+// the HBM traffic is the same; it runs on 512 threads with 32 points of each
+// column a thread, which leaves the registers the matrix-core stages need.  The radix-16 stages
+// run on half of the tile at a time (the even columns, then the odd ones)
+// in LDS: the half is written to LDS in digit-reversed order, every stage
+// reads its B operands from LDS (twiddled and split), contracts them on the
+// matrix cores and writes its outputs back in place, and the result is read
+// back in natural order.  The other half waits in registers.
+// Thread maps: on a unit-stride side the pair index runs fastest across the
+// lanes (runs of adjacent columns), on the other side the row does (runs of
+// one column); the two maps meet through LDS.
+// ---------------------------------------------------------------------------
+namespace {
+
+// x * w (forward) or x * conj(w) (adjoint) for a forward table root w.
+__device__ __forceinline__ float2 cmul_fwd_or_conj(float2 x, float2 w, bool fwd)
+{
+    return fwd ? cmul(x, w) : mkc(x.x * w.x + x.y * w.y, x.y * w.x - x.x * w.y);
+}
+
+// Base-16 digit reversal of an index of NST digits.
+template <int NST>
+__device__ __forceinline__ int rev16(int p)
+{
+    int r = 0;
+#pragma unroll
+    for (int d = 0; d < NST; ++d) {
+        r = (r << 4) | (p & 15);
+        p >>= 4;
+    }
+    return r;
+}
+
+// hi + lo split of one complex value into two packed 32-bit words (re in the
+// low half, im in the high half), as the B operand wants them.
+template <int PREC>
+__device__ __forceinline__ void split_pack(float xr, float xi, uint32_t& hw, uint32_t& lw)
+{
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    if constexpr (PREC == 1) {
+        typedef __bf16 h2v __attribute__((ext_vector_type(2)));
+        hw = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){xr, xi}, h2v));
+        const float hr = __uint_as_float(hw << 16), hi = __uint_as_float(hw & 0xffff0000u);
+        lw = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){xr - hr, xi - hi}, h2v));
+    } else {
+        typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+        const h2v h = __builtin_convertvector((f2v){xr, xi}, h2v);
+        hw = __builtin_bit_cast(uint32_t, h);
+        lw = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){xr - float(h.x), xi - float(h.y)}, h2v));
+    }
+}
+
+// The NST radix-16 stages of the P columns (stride cs) held in LDS, in place
+// by decimation in time: the columns enter in base-16 digit-reversed order
+// and leave in natural order.  Stage s combines the slots that differ in
+// digit s: butterfly j of a block of 16^(s+1) slots reads slots
+// base + j + r 16^s, multiplies input r by omega_{16^(s+1)}^(j r) and writes
+// its output k back to slot base + j + k 16^s.  Each butterfly reads and
+// writes only its own 16 slots, so a wave stores its outputs as soon as the
+// contraction is done, and one barrier ends the stage.  Padded slot
+// base + r 16^s is pad(base) + r * pstep (pstep = 1 at s = 0, else
+// 16^s * 17 / 16).
+template <int LGN, int PREC, bool FWD, typename V8>
+__device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, int pre_lg, int t,
+                                                 const V8 (&ahi)[2], const V8 (&alo)[2])
+{
+    using Sp = SplitT<PREC>;
+    constexpr int N = 1 << LGN;
+    constexpr int NST = LGN / 4;
+    constexpr int NB = N / 16;  // butterflies per column per stage
+    constexpr int GPW = 8;      // 16-butterfly groups per wave: 1024 butterflies, 8 waves
+    const int lane = t & 63, wave = t >> 6, g = lane >> 4;
+    union Op {
+        V8 v;
+        uint32_t w[4];
+    };
+    // One stage body for all stages (not unrolled: that keeps the register
+    // budget); the stage enters as uniform shifts and strides.
+#pragma unroll 1
+    for (int s = 0; s < NST; ++s) {
+        const int lgns = 4 * s, ns = 1 << lgns;
+        const int pstep = s == 0 ? 1 : ns + (ns >> 4);
+        const int tsh = kLgTwBlk - lgns - 4;
+        // Exact power-of-two scaling for fp16 (see the file comment).
+        const int lgscale = PREC == 2 ? (pre_lg + lgns) / 2 : 0;
+        const float down = __builtin_ldexpf(1.0f, -lgscale), up = __builtin_ldexpf(1.0f, lgscale);
+#pragma unroll 2
+        for (int grp = 0; grp < GPW; ++grp) {
+            const int bf = (wave * GPW + grp) * 16 + (lane & 15);
+            const int w = bf >> (LGN - 4), b = bf & (NB - 1);
+            const int jj = b & (ns - 1);
+            float2* pb = lds + w * cs + lds_pad(((b >> lgns) << (lgns + 4)) + jj);
+            Op bhi, blo;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 4 * g + i;
+                float2 x = pb[r * pstep];
+                if (s > 0) x = cmul_fwd_or_conj(x, tw_blk(tl, (jj * r) << tsh), FWD);
+                float xr = x.x, xi = x.y;
+                if constexpr (PREC == 2) {
+                    xr *= down;
+                    xi *= down;
+                }
+                split_pack<PREC>(xr, xi, bhi.w[i], blo.w[i]);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = Sp::mma(ahi[h], bhi.v, acc);
+                acc = Sp::mma(ahi[h], blo.v, acc);
+                acc = Sp::mma(alo[h], bhi.v, acc);
+                if constexpr (PREC == 2) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] *= up;
+                }
+                // rows 4g .. 4g+3 of half h: outputs q = 8h + 2g and 8h + 2g + 1
+                const int q = 8 * h + 2 * g;
+                pb[q * pstep] = mkc(acc[0], acc[1]);
+                pb[(q + 1) * pstep] = mkc(acc[2], acc[3]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ const float2* mat(const char* base, uint32_t off)
+{
+    return reinterpret_cast<const float2*>(base + size_t(off));
+}
+__device__ __forceinline__ float2* mat(char* base, uint32_t off) { return reinterpret_cast<float2*>(base + size_t(off)); }
+
+}  // namespace
+
+template <int LGN, int PREC, bool TIN, bool TOUT, bool FWD>
+__global__ void __launch_bounds__(512) k_pass_mfma_pair(PassArgs a)
+{
+    using V = float2;
+    using Sp = SplitT<PREC>;
+    using S = typename Sp::S;
+    using V8 = typename Sp::V8;
+    constexpr int N = 1 << LGN;
+    constexpr int E = 32;  // points of each column a thread
+    constexpr int LGTPC = LGN - 5, TPC = 1 << LGTPC;
+    constexpr int LGP = 14 - LGN, P = 1 << LGP;  // column pairs of the tile
+    static_assert(LGN == 8 || LGN == 12, "paired-column matrix-core levels of 2^8 or 2^12 points");
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    V* tl = lds + a.data_elems;
+    V* tt = tl + kTwBlkEntries;
+    const int t = threadIdx.x;
+    const int cs = a.col_stride;
+    // (pair, row) of this thread on the input and on the output side.
+    const int ui = TIN ? (t & (P - 1)) : (t >> LGTPC), ji = TIN ? (t >> LGP) : (t & (TPC - 1));
+    const int uo = TOUT ? (t & (P - 1)) : (t >> LGTPC), jo = TOUT ? (t >> LGP) : (t & (TPC - 1));
+
+    V tab[4];
+    const int nt = 256 * (1 + a.tw_parts);
+    {
+        const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
+        const V* g2 = reinterpret_cast<const V*>(a.tw_inter);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = t + 512 * k;
+            if (i < nt) tab[k] = i < 256 ? g1[i] : g2[i - 256];
+        }
+    }
+    uint64_t tile = blockIdx.x;
+    if (a.xcd_remap) tile = uint64_t(blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    int64_t d0, ib, ob;
+    tile_offsets(a, tile, d0, ib, ob);
+    const char* gin = reinterpret_cast<const char*>(a.in) + ib * int64_t(sizeof(V));
+    char* gout = reinterpret_cast<char*>(a.out) + ob * int64_t(sizeof(V));
+
+    V v0[E], v1[E];
+    {
+        const uint32_t se = uint32_t(a.in_s_e) * 8u, s0 = uint32_t(a.in_s[0]) * 8u;
+        const uint32_t step = uint32_t(TPC) * se;
+        if constexpr (TIN) {
+            const uint32_t off = 16u * uint32_t(ui) + uint32_t(ji) * se;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const float4 x = *reinterpret_cast<const float4*>(mat(gin, off + uint32_t(m) * step));
+                v0[m] = make_float2(x.x, x.y);
+                v1[m] = make_float2(x.z, x.w);
+            }
+        } else {
+            const uint32_t o0 = 2u * uint32_t(ui) * s0 + uint32_t(ji) * se, o1 = o0 + s0;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                v0[m] = *mat(gin, o0 + uint32_t(m) * step);
+                v1[m] = *mat(gin, o1 + uint32_t(m) * step);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = t + 512 * k;
+        if (i < nt) tl[i] = tab[k];
+    }
+    V8 ahi[2], alo[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        V* vh = h ? v1 : v0;
+        if (h) __syncthreads();  // the first half has been read back everywhere
+        V* cin = lds + ui * cs;
+#pragma unroll
+        for (int m = 0; m < E; ++m) cin[lds_pad(rev16<LGN / 4>(ji + m * TPC))] = vh[m];
+        __syncthreads();
+        if (h == 0) {
+            // A operand fragments of this lane (two 16-row halves of the real
+            // 32 x 32 DFT matrix, hi and lo parts) from the omega_16 entries
+            // of the in-block table: tl[128 + 8 e] = omega_{2^14}^(1024 e).
+            const int lane = t & 63, g = lane >> 4;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int row = 16 * hh + (lane & 15), col = 8 * g + i;
+                    const int e = ((row >> 1) * (col >> 1)) & 15;
+                    const V w = tl[128 + 8 * e];
+                    const float c = w.x, sn = FWD ? w.y : -w.y;  // forward table: w.y = -sin
+                    const float v = (row & 1) == 0 ? ((col & 1) == 0 ? c : -sn) : ((col & 1) == 0 ? sn : c);
+                    const S hi = S(v);
+                    ahi[hh][i] = hi;
+                    alo[hh][i] = S(v - float(hi));
+                }
+        }
+        mfma_half_stages<LGN, PREC, FWD>(lds, cs, tl, a.pre_lg, t, ahi, alo);
+        const V* cout = lds + uo * cs;
+#pragma unroll
+        for (int m = 0; m < E; ++m) vh[m] = cout[lds_pad(jo + m * TPC)];
+    }
+
+    const uint32_t ju = uint32_t(jo), uu = uint32_t(uo);
+    if (a.tw_parts) {
+        const uint32_t mask = uint32_t((uint64_t(1) << a.tw_lgroot) - 1);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            V* v = c ? v1 : v0;
+            const uint32_t dcol = uint32_t(d0) + 2u * uu + uint32_t(c);
+            V f[E];
+            f[0] = tw_inter32(tt, a.tw_parts, (dcol * ju) & mask);
+            V pw[5];
+#pragma unroll
+            for (int b = 0; b < 5; ++b) pw[b] = tw_inter32(tt, a.tw_parts, (dcol * (uint32_t(TPC) << b)) & mask);
+            power_tree<5, false>(f, pw);
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = cmul_fwd_or_conj(v[m], f[m], FWD);
+        }
+    }
+    const uint32_t sk = uint32_t(a.out_s_k) * 8u, s0 = uint32_t(a.out_s[0]) * 8u;
+    const uint32_t step = uint32_t(TPC) * sk;
+    if constexpr (TOUT) {
+        const uint32_t off = 16u * uu + ju * sk;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            *reinterpret_cast<float4*>(mat(gout, off + uint32_t(m) * step)) =
+                make_float4(v0[m].x, v0[m].y, v1[m].x, v1[m].y);
+    } else {
+        const uint32_t o0 = 2u * uu * s0 + ju * sk, o1 = o0 + s0;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            *mat(gout, o0 + uint32_t(m) * step) = v0[m];
+            *mat(gout, o1 + uint32_t(m) * step) = v1[m];
+        }
+    }
+}
+
 using PassFn = void (*)(PassArgs);
 
 #define MOA_MFMA_ROW(L) \
@@ -267,19 +539,43 @@ static PassFn mfma_lookup(int lgn, int prec)
     return kMfma[lgn / 4 - 1][prec - 1];
 }
 
-const void* mfma_kernel_fn(const PassDesc& d) { return reinterpret_cast<const void*>(mfma_lookup(d.lgn, d.mfma)); }
+#define MOA_MP(L, PR, F) \
+    { {&k_pass_mfma_pair<L, PR, false, false, F>, &k_pass_mfma_pair<L, PR, false, true, F>}, \
+      {&k_pass_mfma_pair<L, PR, true, false, F>, &k_pass_mfma_pair<L, PR, true, true, F>} }
+// [lgn 8 / 12][prec - 1][direction][tin][tout]; 512 threads
+static const PassFn kMfmaPair[2][2][2][2][2] = {
+    {{MOA_MP(8, 1, true), MOA_MP(8, 1, false)}, {MOA_MP(8, 2, true), MOA_MP(8, 2, false)}},
+    {{MOA_MP(12, 1, true), MOA_MP(12, 1, false)}, {MOA_MP(12, 2, true), MOA_MP(12, 2, false)}},
+};
+
+static PassFn mfma_pair_lookup(const PassDesc& d, bool fwd)
+{
+    if ((d.lgn != 8 && d.lgn != 12) || d.mfma < 1 || d.mfma > 2) return nullptr;
+    return kMfmaPair[d.lgn == 12][d.mfma - 1][fwd ? 0 : 1][d.in_tile_fast][d.out_tile_fast];
+}
+
+static PassFn mfma_fn(const PassDesc& d, bool fwd)
+{
+    return d.kmode == 3 ? mfma_pair_lookup(d, fwd) : mfma_lookup(d.lgn, d.mfma);
+}
+
+const void* mfma_kernel_fn(const PassDesc& d, bool fwd) { return reinterpret_cast<const void*>(mfma_fn(d, fwd)); }
 
 hipError_t prepare_mfma_kernel(const PassDesc& d)
 {
-    PassFn f = mfma_lookup(d.lgn, d.mfma);
-    if (!f) return hipErrorInvalidValue;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               d.lds_bytes);
+    for (bool fwd : {true, false}) {
+        PassFn f = mfma_fn(d, fwd);
+        if (!f) return hipErrorInvalidValue;
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_mfma(const PassDesc& d, const PassArgs& a, hipStream_t s)
 {
-    PassFn f = mfma_lookup(d.lgn, d.mfma);
+    PassFn f = mfma_fn(d, a.sign < 0.f);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);
     return hipGetLastError();

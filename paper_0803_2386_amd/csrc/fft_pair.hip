@@ -167,26 +167,26 @@ __device__ __forceinline__ void pair_tile(const PassArgs& a, uint64_t tile)
     // Inter-level factor omega^(dcol * (j + rank * TPC)): base times the
     // powers omega^(dcol * TPC * 2^b) of the set bits b of rank.  The root
     // is at most 2^32 (planner), so exponents wrap in 32-bit arithmetic.
-    if (a.tw_parts) {
-        const uint32_t mask = uint32_t((uint64_t(1) << a.tw_lgroot) - 1);
+    const uint32_t mask = uint32_t((uint64_t(1) << a.tw_lgroot) - 1);
+    auto twiddle = [&](V* v, int c) {
+        const uint32_t dcol = uint32_t(d0) + 2u * uu + uint32_t(c);
+        V f[E];
+        f[0] = tw_inter32(tt, a.tw_parts, (dcol * ju) & mask);
+        V pw[4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            V* v = c ? v1 : v0;
-            const uint32_t dcol = uint32_t(d0) + 2u * uu + uint32_t(c);
-            V f[E];
-            f[0] = tw_inter32(tt, a.tw_parts, (dcol * ju) & mask);
-            V pw[4];
+        for (int b = 0; b < 4; ++b) pw[b] = tw_inter32(tt, a.tw_parts, (dcol * (uint32_t(TPC) << b)) & mask);
+        power_tree<4, false>(f, pw);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) pw[b] = tw_inter32(tt, a.tw_parts, (dcol * (uint32_t(TPC) << b)) & mask);
-            power_tree<4, false>(f, pw);
-#pragma unroll
-            for (int m = 0; m < E; ++m) v[m] = cmul_dir<FWD>(v[m], f[out_slot_rank<LGN, 4>(m)]);
-        }
-    }
+        for (int m = 0; m < E; ++m) v[m] = cmul_dir<FWD>(v[m], f[out_slot_rank<LGN, 4>(m)]);
+    };
 
     const uint32_t sk = uint32_t(a.out_s_k) * 8u, s0 = uint32_t(a.out_s[0]) * 8u;
     const uint32_t step = uint32_t(TPC) * sk;
     if constexpr (TOUT) {
+        if (a.tw_parts) {
+            twiddle(v0, 0);
+            twiddle(v1, 1);
+        }
         const uint32_t off = 16u * uu + ju * sk;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -194,13 +194,14 @@ __device__ __forceinline__ void pair_tile(const PassArgs& a, uint64_t tile)
             *reinterpret_cast<float4*>(at(gout, o)) = make_float4(v0[m].x, v0[m].y, v1[m].x, v1[m].y);
         }
     } else {
-        const uint32_t o0 = 2u * uu * s0 + ju * sk;
-        const uint32_t o1 = o0 + s0;
+        // One column at a time: its factors and stores, then the next.
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const uint32_t r = uint32_t(out_slot_rank<LGN, 4>(m)) * step;
-            *at(gout, o0 + r) = v0[m];
-            *at(gout, o1 + r) = v1[m];
+        for (int c = 0; c < 2; ++c) {
+            V* v = c ? v1 : v0;
+            if (a.tw_parts) twiddle(v, c);
+            const uint32_t o = 2u * uu * s0 + ju * sk + uint32_t(c) * s0;
+#pragma unroll
+            for (int m = 0; m < E; ++m) *at(gout, o + uint32_t(out_slot_rank<LGN, 4>(m)) * step) = v[m];
         }
     }
 }

@@ -29,14 +29,20 @@ def check_pass(p, total, elem_bytes):
     pair = p["kernel_mode"] == 3
     E = min(N, p["points_per_thread"]) if not mfma else 1
     if pair:
-        E = 16  # per column; each thread owns two adjacent columns
+        # each thread owns two adjacent columns: 16 points of each (FP32
+        # kernel, 1024 threads) or 32 (matrix-core kernel, 512 threads)
+        E = 32 if mfma else 16
     TPC = N // E
     W = p["tile_width"]
     T = p["threads"]
     if pair:
-        assert elem_bytes == 8 and 12 <= N.bit_length() - 1 <= 14 and W * N == 1 << 15
-        assert T == 1024 == (W // 2) * TPC
-        assert p["in_tile_fast"] or p["out_tile_fast"]
+        lgn = N.bit_length() - 1
+        assert elem_bytes == 8 and W * N == 1 << 15
+        assert T == (W // 2) * TPC == (512 if mfma else 1024)
+        if mfma:
+            assert lgn in (8, 12)
+        else:
+            assert 12 <= lgn <= 14 and (p["in_tile_fast"] or p["out_tile_fast"])
     elif mfma:
         # 32 points a thread, copied in and out over i = t + m T
         assert T * 32 == W * N and T % 64 == 0 and T <= 512
@@ -83,9 +89,14 @@ def check_pass(p, total, elem_bytes):
         ob = ob + idx * axes[d]["out_stride"]
     t = np.arange(T)
     if pair:
-        # pair index fastest on both sides; columns 2u and 2u + 1
+        # pair index fastest on a unit-stride side (the FP32 kernel uses that
+        # map on both sides), row fastest on the other side of a matrix-core
+        # level; columns 2u and 2u + 1
         P = W // 2
-        u, j = t % P, t // P
+        if mfma and not p["in_tile_fast"]:
+            j, u = t % TPC, t // TPC
+        else:
+            u, j = t % P, t // P
         w = np.concatenate([2 * u, 2 * u + 1])
         j = np.concatenate([j, j])
     elif p["in_tile_fast"]:
@@ -170,7 +181,8 @@ def test_mfma_pass_geometry(n, batch, lift, prec):
     d = _check_plan(h, n, batch, capi.MOA_C64)
     for p in d["passes"]:
         if p["mfma"] != "none":
-            assert p["threads"] % 64 == 0 and p["threads"] == p["tile_width"] * p["N"] // 32
+            per_thread = 64 if p["kernel_mode"] == 3 else 32
+            assert p["threads"] % 64 == 0 and p["threads"] == p["tile_width"] * p["N"] // per_thread
 
 
 def _check_plan(h, n, batch, dtype):
@@ -223,3 +235,57 @@ def test_batched_task_geometry():
             assert per * cs * 8 + 256 * 8 <= d["lds_bytes"]
         assert g["tasks"] == -(-sizes.count(N) // per)
     assert d["tasks"] == sum(g["tasks"] for g in d["sizes_by_task_group"])
+
+
+@pytest.mark.parametrize("lgn", [4, 8, 12])
+def test_mfma_pair_stage_indexing(lgn):
+    """numpy mirror of the in-place radix-16 stages of the paired-column
+    matrix-core kernel: the columns enter LDS in base-16 digit-reversed order;
+    stage s, butterfly b (block b >> 4s, j = b mod 16^s) reads padded slots
+    pad(base) + r * pstep, multiplies input r by omega_{16^(s+1)}^(j r) and
+    writes output k to pad(base) + k * pstep; after the last stage slot k holds
+    X[k].  Checks the slot sets (each slot read and written once a stage, the
+    padded step equals pad(base + r 16^s) - pad(base)), the lane split of the
+    16x16x32 operands (lane group g reads inputs 4g..4g+3 and writes outputs
+    2g, 2g+1, 8+2g, 9+2g) and the result against numpy's FFT."""
+    N = 1 << lgn
+    nst, nb = lgn // 4, N // 16
+
+    def rev16(p):
+        r = 0
+        for _ in range(nst):
+            r, p = (r << 4) | (p & 15), p >> 4
+        return r
+
+    rng = np.random.default_rng(lgn)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    slots = np.zeros(pad(N - 1) + 1, complex)
+    for p in range(N):
+        slots[pad(rev16(p))] = x[p]
+    F16 = np.exp(-2j * np.pi * np.outer(np.arange(16), np.arange(16)) / 16)
+    for s in range(nst):
+        ns = 1 << (4 * s)
+        pstep = 1 if s == 0 else ns + (ns >> 4)
+        read = np.zeros_like(slots, dtype=int)
+        written = np.zeros_like(slots, dtype=int)
+        new = slots.copy()
+        for b in range(nb):
+            j = b & (ns - 1)
+            base = ((b >> (4 * s)) << (4 * s + 4)) + j
+            pb = pad(base)
+            for r in range(16):
+                assert pad(base + r * ns) == pb + r * pstep
+            idx = pb + np.arange(16) * pstep
+            # lane group g holds inputs 4g..4g+3 and outputs {2g, 2g+1, 8+2g, 9+2g}
+            ins = sorted(4 * g + i for g in range(4) for i in range(4))
+            outs = sorted(q for g in range(4) for q in (2 * g, 2 * g + 1, 8 + 2 * g, 9 + 2 * g))
+            assert ins == list(range(16)) and outs == list(range(16))
+            read[idx] += 1
+            written[idx] += 1
+            xin = slots[idx] * np.exp(-2j * np.pi * j * np.arange(16) / (16 * ns))
+            new[idx] = F16 @ xin
+        used = np.array([pad(i) for i in range(N)])
+        assert np.all(read[used] == 1) and np.all(written[used] == 1)
+        slots = new
+    got = np.array([slots[pad(k)] for k in range(N)])
+    assert np.abs(got - np.fft.fft(x)).max() < 1e-9 * N
