@@ -159,15 +159,18 @@ moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, v
  * `in`, later levels read the plan's workspace; the last level writes
  * `out`, earlier ones the workspace.  Running levels 0..L-1 in order equals
  * moa_fft_exec.  For timing and inspecting one level of the lift
- * ("The General Algorithm": one level = one pass over memory).  Errors as
- * moa_fft_exec, plus MOA_ERR_ARG for a level outside 0..L-1 or an uneven
- * batch plan.
+ * ("The General Algorithm": one level = one pass over memory).  For an
+ * uneven batch planned with MOA_FFT_FLAG_PER_SIZE, level g runs the
+ * transforms of the g-th distinct length (longest first) from `in` to `out`;
+ * for the persistent form level 0 is the whole launch.  Errors as
+ * moa_fft_exec, plus MOA_ERR_ARG for a level outside 0..L-1.
  */
 moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t level, const void* in,
                                 void* out, void* stream);
 
 /* Number of levels (= kernel launches per execution) of a plan; 1 for an
- * uneven batch in one persistent launch. */
+ * uneven batch in one persistent launch, the number of distinct lengths for
+ * one planned with MOA_FFT_FLAG_PER_SIZE. */
 moa_status_t moa_fft_num_levels(moa_fft_plan_t p, int32_t* levels);
 
 /* Bytes of device workspace the plan owns (0 for single-level plans). */

@@ -12,17 +12,21 @@
 
 namespace moa {
 
-// A task is up to 2^13 points -- count transforms of 2^lgn points side by
-// side on 512 threads, 16 points a thread, or one whole transform a thread
-// when it is shorter than that -- or one complex64 transform of 2^14 points,
-// 32 points a thread.
+// A task is up to 2^13 points: count transforms of 2^lgn points side by side
+// on 512 threads, 16 points a thread, or one whole transform a thread when it
+// is shorter than that.  A complex64 transform of 2^14 points is one task
+// too: the DFTs of its even and of its odd samples (2^13 points each, one
+// after the other in the same LDS tile) and one radix-2 step in registers,
+// the first decimation-in-time split of Fig. vanloan_fft.  So every task
+// fits half of the LDS and two workgroups share each CU, one moving data
+// while the other computes.
 // Thread t owns column w = t / TPC, rows j + m TPC (j = t mod TPC): the
 // stage-0 register layout of the level kernel, which also reads and writes
 // each transform in runs of consecutive elements, so no LDS pass is needed
 // around the stages.
 template <typename R, int LGN>
-__host__ __device__ constexpr int task_lge() { return (sizeof(R) == 4 && LGN == 14) ? 5 : 4; }
-constexpr int kTaskPts = 32;  // register slots per thread
+__host__ __device__ constexpr int task_lge() { return 4; }
+constexpr int kTaskPts = 16;  // register slots per thread
 
 // Loads of this thread's points of a task of 2^LGN-point transforms (slot
 // order of stage 0); `off` is the element offset of the thread's transform.
@@ -80,66 +84,113 @@ __device__ __forceinline__ void task_run(typename cpx<R>::V (&v)[kTaskPts], type
         default: break;            \
     }
 
+// One 2^14-point complex64 transform at element offset `off` (512 threads):
+// e = its even samples, o = its odd samples, 16 points of each a thread,
+// transformed together as the two columns of a paired tile (their exchanges
+// take turns in the one LDS column), then
+// X[k] = E[k] + w^k O[k], X[k + 2^13] = E[k] - w^k O[k], w = omega_{2^14}.
+template <bool FWD>
+__device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, float2* lds, const float2* tl, int t)
+{
+    using V = float2;
+    constexpr int LGH = 13, TPC = 512, E = 16;
+    const V* __restrict__ src = reinterpret_cast<const V*>(a.in) + off;
+    V* __restrict__ dst = reinterpret_cast<V*>(a.out) + off;
+    V e[E], o[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = 2 * (t + m * TPC);
+        e[in_slot<LGH, 4>(m)] = src[i];
+        o[in_slot<LGH, 4>(m)] = src[i + 1];
+    }
+    pair_stages<FWD, LGH, 0>(e, o, lds, t, tl);
+    // w^k for k = t + rank * TPC: base w^t times the powers w^(TPC 2^b) of
+    // the set bits b of rank.
+    V f[E], pw[4];
+    f[0] = tw_blk(tl, t);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) pw[b] = tw_blk(tl, TPC << b);
+    power_tree<4, false>(f, pw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int rank = out_slot_rank<LGH, 4>(m);
+        const V p = cmul_dir<FWD>(o[m], f[rank]);
+        dst[t + rank * TPC] = cadd(e[m], p);
+        dst[t + rank * TPC + (1 << LGH)] = csub(e[m], p);
+    }
+}
+
 // The run of this workgroup's tasks (ti, ti + G, ...) that hold transforms
-// of 2^LGN points; returns the first task of the run's end.  Within the run
-// the next task's points are loading into registers while the current one is
-// transformed (complex64), so the HBM traffic of one task overlaps the work
-// of the previous one.  The longest-first task order makes each workgroup's
-// walk a few such runs.
-template <typename R, int LGN>
+// of 2^LGN points; returns the first task of the run's end.  The
+// longest-first task order makes each workgroup's walk a few such runs.
+template <typename R, bool FWD, int LGN>
 __device__ __forceinline__ int batch_run(const BatchArgs& a, int ti, typename cpx<R>::V* lds,
-                                      const typename cpx<R>::V* tl, int t)
+                                         const typename cpx<R>::V* tl, int t)
 {
     using V = typename cpx<R>::V;
     constexpr int LGE = task_lge<R, LGN>();
     constexpr int LGTPC = LGN - lg_e(LGN, LGE);
-    constexpr bool kPF = sizeof(R) == 4;  // complex128 batches are for accuracy: no prefetch
-    const V* __restrict__ in = reinterpret_cast<const V*>(a.in);
-    V* __restrict__ out = reinterpret_cast<V*>(a.out);
     const int end = a.task0 + a.ntasks;
     const int G = gridDim.x;
     auto same = [&](int task) { return task < end && a.tasks[task].lgn == LGN; };
-    auto fetch = [&](int task, V (&dst)[kTaskPts], int64_t& o, bool& act) {
-        const BatchTask tk = a.tasks[task];
-        const int w = t >> LGTPC;
-        act = w < tk.count;
-        o = act ? a.toff[tk.first + w] : 0;
-        if (act) task_load<R, LGN>(dst, in, o, t);
-    };
-    V v[kTaskPts];
-    int64_t off = 0;
-    bool active = false;
-    if (kPF) fetch(ti, v, off, active);
     int tt = t;
-    for (; same(ti); ti += G) {
-        // Keep the stage addresses (all derived from the thread index) out of
-        // reach of loop-invariant code motion, which would hold them in VGPRs.
-        asm volatile("" : "+v"(tt));
-        V vn[kTaskPts];
-        int64_t noff = 0;
-        bool nact = false;
-        const bool more = same(ti + G);
-        if (kPF) {
-            if (more) fetch(ti + G, vn, noff, nact);
-        } else {
-            fetch(ti, v, off, active);
+    if constexpr (LGN == 14 && sizeof(R) == 4) {
+        for (; same(ti); ti += G) {
+            asm volatile("" : "+v"(tt));
+            split14_run<FWD>(a, a.toff[a.tasks[ti].first], lds, tl, tt);
+            __syncthreads();  // the next task overwrites the LDS exchange area
         }
-        task_run<R, LGN>(v, out, off, active, lds, tl, R(a.sign), tt);
-        __syncthreads();  // the next task overwrites the LDS exchange area
-        if (kPF && more) {
+        return ti;
+    } else {
+        // No register prefetch: the second resident workgroup of the CU
+        // overlaps this one's memory phases, and the registers it would need
+        // are what let two workgroups fit.
+        constexpr bool kPF = false;
+        const V* __restrict__ in = reinterpret_cast<const V*>(a.in);
+        V* __restrict__ out = reinterpret_cast<V*>(a.out);
+        auto fetch = [&](int task, V (&dst)[kTaskPts], int64_t& o, bool& act) {
+            const BatchTask tk = a.tasks[task];
+            const int w = t >> LGTPC;
+            act = w < tk.count;
+            o = act ? a.toff[tk.first + w] : 0;
+            if (act) task_load<R, LGN>(dst, in, o, t);
+        };
+        V v[kTaskPts];
+        int64_t off = 0;
+        bool active = false;
+        if (kPF) fetch(ti, v, off, active);
+        for (; same(ti); ti += G) {
+            // Keep the stage addresses (all derived from the thread index) out
+            // of reach of loop-invariant code motion, which would hold them in
+            // VGPRs.
+            asm volatile("" : "+v"(tt));
+            V vn[kTaskPts];
+            int64_t noff = 0;
+            bool nact = false;
+            const bool more = same(ti + G);
+            if (kPF) {
+                if (more) fetch(ti + G, vn, noff, nact);
+            } else {
+                fetch(ti, v, off, active);
+            }
+            task_run<R, LGN>(v, out, off, active, lds, tl, R(a.sign), tt);
+            __syncthreads();  // the next task overwrites the LDS exchange area
+            if (kPF && more) {
 #pragma unroll
-            for (int m = 0; m < (1 << lg_e(LGN, LGE)); ++m) v[m] = vn[m];
-            off = noff;
-            active = nact;
+                for (int m = 0; m < (1 << lg_e(LGN, LGE)); ++m) v[m] = vn[m];
+                off = noff;
+                active = nact;
+            }
         }
+        return ti;
     }
-    return ti;
 }
 
 // Persistent uneven batch: each workgroup walks the tasks blockIdx.x,
-// blockIdx.x + G, ... as runs of equal transform length.
-template <typename R>
-__global__ void __launch_bounds__(512) k_batched(BatchArgs a)
+// blockIdx.x + G, ... as runs of equal transform length; two workgroups are
+// resident on each CU (complex64).
+template <typename R, bool FWD>
+__global__ void __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) k_batched(BatchArgs a)
 {
     using V = typename cpx<R>::V;
     constexpr int kMaxLg = sizeof(R) == 8 ? kMaxLgBlockC128 : kMaxLgBlockC64;
@@ -158,30 +209,35 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
         const int lgn = a.tasks[ti].lgn;
         int nti = end;
 #define MOA_RUN(L) \
-    if constexpr (L <= kMaxLg) nti = batch_run<R, L>(a, ti, lds, tl, t)
+    if constexpr (L <= kMaxLg) nti = batch_run<R, FWD, L>(a, ti, lds, tl, t)
         MOA_TASK_SWITCH(lgn, MOA_RUN)
 #undef MOA_RUN
         ti = nti;
     }
 }
 
-const void* batched_kernel_fn(bool fp64)
+using BatchFn = void (*)(BatchArgs);
+static BatchFn batched_lookup(bool fp64, bool fwd)
 {
-    return fp64 ? reinterpret_cast<const void*>(&k_batched<double>)
-                : reinterpret_cast<const void*>(&k_batched<float>);
+    if (fp64) return fwd ? &k_batched<double, true> : &k_batched<double, false>;
+    return fwd ? &k_batched<float, true> : &k_batched<float, false>;
 }
+
+const void* batched_kernel_fn(bool fp64, bool fwd) { return reinterpret_cast<const void*>(batched_lookup(fp64, fwd)); }
 
 hipError_t prepare_batched_kernel(bool fp64, int lds_bytes)
 {
-    return hipFuncSetAttribute(batched_kernel_fn(fp64), hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    for (bool fwd : {true, false}) {
+        const hipError_t e = hipFuncSetAttribute(batched_kernel_fn(fp64, fwd),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_batched(bool fp64, const BatchArgs& a, int grid, int threads, int lds_bytes, hipStream_t s)
 {
-    if (fp64)
-        hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(threads), lds_bytes, s, a);
-    else
-        hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(threads), lds_bytes, s, a);
+    hipLaunchKernelGGL(batched_lookup(fp64, a.sign < 0.f), dim3(grid), dim3(threads), lds_bytes, s, a);
     return hipGetLastError();
 }
 

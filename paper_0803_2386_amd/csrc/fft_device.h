@@ -408,6 +408,69 @@ __device__ __forceinline__ void tile_offsets(const PassArgs& a, uint64_t tile_id
     }
 }
 
+// Stage S of two 16-point-per-thread transforms of 2^LGN points held side by
+// side (v0 and v1: the even and odd column of a paired-column tile, or the
+// even and odd samples of one longer transform); slot layout as in
+// run_stages (LGE = 4).  The two share the stage twiddles and one LDS
+// column: each exchange runs v0 through it, then v1.  Every stage
+// but the last is radix 16 with one butterfly a thread (NB = 1), so each LDS
+// slot a thread touches is its padded base slot plus a constant.
+template <bool FWD, int LGN, int S>
+__device__ __forceinline__ void pair_stages(float2* v0, float2* v1, float2* col, int j, const float2* twb)
+{
+    constexpr int NST = n_stages(LGN);
+    using I = StageTw<LGN, 4, S>;
+    constexpr int N = I::N, LGR = I::LGR, RS = I::RS, LGNS = I::LGNS, NS = I::NS, TPC = I::TPC, NB = I::NB;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if constexpr (NS > 1) {
+            // omega_{NS RS}^(bm r) for r < RS from the table powers r = 2^b.
+            const int bm = (j + q * TPC) & (NS - 1);
+            const int e1 = bm << (kLgTwBlk - LGNS - LGR);
+            float2 pw[LGR];
+#pragma unroll
+            for (int b = 0; b < LGR; ++b) pw[b] = tw_blk(twb, e1 << b);
+            float2 f[RS];
+            power_tree<LGR, true>(f, pw);
+#pragma unroll
+            for (int r = 1; r < RS; ++r) {
+                v0[q * RS + r] = cmul_dir<FWD>(v0[q * RS + r], f[r]);
+                v1[q * RS + r] = cmul_dir<FWD>(v1[q * RS + r], f[r]);
+            }
+        }
+        dft_dir<FWD, float, LGR>(v0 + q * RS);
+        dft_dir<FWD, float, LGR>(v1 + q * RS);
+    }
+    if constexpr (S + 1 < NST) {
+        static_assert(NB == 1 && RS == 16, "inner stages are radix 16");
+        using J = StageTw<LGN, 4, S + 1>;
+        // Output r of the butterfly goes to Stockham slot base + r NS.
+        const int base = ((j >> LGNS) << (LGNS + LGR)) + (j & (NS - 1));
+        float2* wp = col + lds_pad(base);
+        auto put = [&](const float2* v) {
+#pragma unroll
+            for (int r = 0; r < RS; ++r) wp[NS == 1 ? r : lds_pad(r * NS)] = v[r];
+        };
+        // Input r of butterfly q of the next stage is row j + q TPC + r N / RS'.
+        float2* rp = col + lds_pad(j);
+        auto get = [&](float2* v) {
+#pragma unroll
+            for (int q = 0; q < J::NB; ++q)
+#pragma unroll
+                for (int r = 0; r < J::RS; ++r) v[q * J::RS + r] = rp[lds_pad(q * TPC + r * (N / J::RS))];
+        };
+        if constexpr (S > 0) __syncthreads();  // the last exchange has been read everywhere
+        put(v0);
+        __syncthreads();
+        get(v0);
+        __syncthreads();
+        put(v1);
+        __syncthreads();
+        get(v1);
+        pair_stages<FWD, LGN, S + 1>(v0, v1, col, j, twb);
+    }
+}
+
 // Position, in units of TPC past the thread's row j, of the output element
 // held in register slot m after the last stage.
 template <int LGN, int LGE>

@@ -138,6 +138,6 @@ hipError_t prepare_pair_kernel(const PassDesc& d);
 const void* pair_kernel_fn(const PassDesc& d, bool fwd);
 // The kernel function pointers, used to build HIP graph nodes.
 const void* pass_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
-const void* batched_kernel_fn(bool fp64);
+const void* batched_kernel_fn(bool fp64, bool fwd);
 
 }  // namespace moa

@@ -598,13 +598,13 @@ moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, G
         if (p->flags & MOA_FFT_FLAG_PER_SIZE) {
             for (const auto& r : p->size_ranges) {
                 moa::BatchArgs a = batch_args(p, dir, in, out, r.first, r.second);
-                st = add_node(g.graph, &prev, moa::batched_kernel_fn(p->fp64), dim3(unsigned(r.second)),
+                st = add_node(g.graph, &prev, moa::batched_kernel_fn(p->fp64, dir == MOA_FFT_FORWARD), dim3(unsigned(r.second)),
                               dim3(unsigned(p->batch_threads)), p->batch_lds, &a);
                 if (st != MOA_OK) break;
             }
         } else {
             moa::BatchArgs a = batch_args(p, dir, in, out, 0, int(p->tasks.size()));
-            st = add_node(g.graph, &prev, moa::batched_kernel_fn(p->fp64), dim3(unsigned(p->batch_grid)),
+            st = add_node(g.graph, &prev, moa::batched_kernel_fn(p->fp64, dir == MOA_FFT_FORWARD), dim3(unsigned(p->batch_grid)),
                           dim3(unsigned(p->batch_threads)), p->batch_lds, &a);
         }
     } else {
@@ -633,7 +633,7 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     const size_t eb = elem_bytes(p->fp64);
     // Tasks of up to 2^13 points on 512 threads, 16 points a thread (one
     // transform a thread when it is shorter than that), or one complex64
-    // transform of 2^14 points, 32 points a thread.
+    // transform of 2^14 points as two halves of 2^13.
     const int T = 512;
     const int64_t count = int64_t(p->sizes.size());
     std::vector<int64_t> off(size_t(count) + 1, 0);
@@ -652,10 +652,13 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     for (int lg = maxlg; lg >= 0; --lg) {
         const auto& idx = by_lg[size_t(lg)];
         if (idx.empty()) continue;
-        const int lge = (!p->fp64 && lg == 14) ? 5 : 4;
-        const int tpc = 1 << (lg - lgE(lg, lge));
-        const int cs = moa::lds_col_stride(1 << lg, tpc);
-        const int per = T / tpc;  // 2^(13 - lg) transforms of 16 points or more, T shorter ones
+        // A 2^14-point complex64 transform runs as its two 2^13-point halves
+        // (even and odd samples) in one task, so its LDS tile is theirs.
+        const bool split = !p->fp64 && lg == 14;
+        const int lgt = split ? 13 : lg;
+        const int tpc = 1 << (lgt - lgE(lgt, 4));
+        const int cs = moa::lds_col_stride(1 << lgt, tpc);
+        const int per = split ? 1 : T / tpc;  // 2^(13 - lg) transforms of 16 points or more, T shorter ones
         const bool uses_lds = lg > 4;  // a single register stage needs no exchange
         const int first_task = int(p->tasks.size());
         for (size_t k = 0; k < idx.size(); k += size_t(per)) {
@@ -868,7 +871,23 @@ moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t lev
 {
     if (!valid_plan(p) || !in || !out) return MOA_ERR_NULL;
     if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
-    if (p->batched || level < 0 || size_t(level) >= p->passes.size()) return MOA_ERR_ARG;
+    if (p->host_only && !p->batched && level >= 0 && size_t(level) < p->passes.size()) return MOA_ERR_STATE;
+    if (p->batched) {
+        // An uneven batch: level = one size group of a per-size plan, or the
+        // single persistent launch (level 0).
+        const bool per_size = (p->flags & MOA_FFT_FLAG_PER_SIZE) != 0;
+        const int groups = per_size ? int(p->size_ranges.size()) : 1;
+        if (level < 0 || level >= groups) return MOA_ERR_ARG;
+        if (p->host_only) return MOA_ERR_STATE;
+        const int task0 = per_size ? p->size_ranges[size_t(level)].first : 0;
+        const int ntasks = per_size ? p->size_ranges[size_t(level)].second : int(p->tasks.size());
+        moa::BatchArgs a = batch_args(p, int(dir), in, out, task0, ntasks);
+        return moa::launch_batched(p->fp64, a, per_size ? ntasks : p->batch_grid, p->batch_threads, p->batch_lds,
+                                   static_cast<hipStream_t>(stream)) == hipSuccess
+                   ? MOA_OK
+                   : MOA_ERR_HIP;
+    }
+    if (level < 0 || size_t(level) >= p->passes.size()) return MOA_ERR_ARG;
     if (p->host_only) return MOA_ERR_STATE;
     if (!pair_aligned(p->passes[size_t(level)], in, out, true, true)) return MOA_ERR_ARG;
     std::vector<moa::PassArgs> args;

@@ -223,3 +223,21 @@ def test_batched_plan_partitions_the_transforms():
     assert [g["n"] for g in groups] == sorted(set(sizes), reverse=True)
     assert sum(g["tasks"] for g in groups) == d["tasks"]
     assert d["lds_bytes"] <= 160 * 1024 and d["threads"] == 512
+
+
+def test_batched_exec_level_validation():
+    """exec_level on an uneven batch: host-only plans cannot run, levels are
+    the size groups of a per-size plan (one level for the persistent form)."""
+    sizes = [64, 4096, 64, 16384, 1]
+    for flags, groups in ((capi.MOA_FFT_FLAG_PER_SIZE, 4), (0, 1)):
+        h = capi.moa_fft_plan_batched(sizes, flags=HOST | flags)
+        try:
+            assert capi.moa_fft_num_levels(h) == groups
+            lib = capi.load()
+            buf = ctypes.c_void_p(16)
+            assert lib.moa_fft_exec_level(h, 0, groups, buf, buf, None) == capi.MOA_ERR_ARG
+            assert lib.moa_fft_exec_level(h, 0, -1, buf, buf, None) == capi.MOA_ERR_ARG
+            assert lib.moa_fft_exec_level(h, 0, 0, buf, buf, None) == capi.MOA_ERR_STATE
+        finally:
+            capi.moa_fft_destroy(h)
+

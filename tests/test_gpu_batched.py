@@ -74,3 +74,25 @@ def test_persistent_grid_smaller_than_tasks():
     need_gpu()
     sizes = [1 << (6 + (i % 9)) for i in range(300)]
     check(sizes, seed=4, threads=4, tuning=dict(persistent_blocks=7))
+
+
+def test_per_size_levels_compose_to_the_batch():
+    """Running the size groups of a per-size plan one by one (exec_level)
+    writes every transform once and equals the whole execution."""
+    need_gpu()
+    sizes = [int(s) for s in inputs.uneven_sizes(300, 0, 14, seed=5)]
+    x = torch.from_numpy(inputs.uniform_complex(sum(sizes), seed=6, dtype=np.complex64)).cuda()
+    plan = mfft.BatchedPlan(sizes, per_size=True)
+    want = plan.forward(x)
+    got = torch.zeros_like(x)
+    assert plan.num_levels == len(set(sizes))
+    for g in range(plan.num_levels):
+        plan.run_level(g, x, got)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    whole = mfft.BatchedPlan(sizes)
+    assert whole.num_levels == 1
+    got2 = torch.zeros_like(x)
+    whole.run_level(0, x, got2)
+    torch.cuda.synchronize()
+    assert torch.equal(got2, whole.forward(x))

@@ -220,17 +220,19 @@ def test_batched_task_geometry():
     finally:
         capi.moa_fft_destroy(h)
     # every task fits the workgroup and the LDS the launch requests: up to
-    # 2^13 points at 16 a thread (one transform a thread below 16 points) or
-    # one 2^14-point transform at 32 a thread, on 512 threads
-    assert d["threads"] == 512 and d["lds_bytes"] <= 160 * 1024
+    # 2^13 points at 16 a thread (one transform a thread below 16 points), a
+    # 2^14-point transform as its two 2^13-point halves, on 512 threads; two
+    # workgroups fit one CU
+    assert d["threads"] == 512 and 2 * d["lds_bytes"] <= 160 * 1024
     for g in d["sizes_by_task_group"]:
         N = g["n"]
         lgn = N.bit_length() - 1
-        TPC = N >> min(lgn, 5 if lgn >= 14 else 4)
-        base = N + (N >> 4)
+        Nt = min(N, 1 << 13)
+        TPC = Nt >> min(Nt.bit_length() - 1, 4)
+        base = Nt + (Nt >> 4)
         cs = base if TPC >= 16 else base + ((TPC - (base & 31) + 32) & 31)
-        per = 512 // TPC
-        assert per * min(N, 16 if lgn < 14 else 32) <= (1 << 14)
+        per = 1 if lgn == 14 else 512 // TPC
+        assert per * min(Nt, 16) <= (1 << 13)
         if lgn > 4:  # more than one register stage: LDS exchange tile
             assert per * cs * 8 + 256 * 8 <= d["lds_bytes"]
         assert g["tasks"] == -(-sizes.count(N) // per)
