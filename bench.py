@@ -79,6 +79,57 @@ def level_times_in_chain(plan, x, out, reps, torch):
     return [sum(ev[r][lvl].elapsed_time(ev[r][lvl + 1]) for r in range(reps)) / reps for lvl in range(levels)]
 
 
+def step_percentiles(fn, reps, torch, np):
+    """p10 / p50 / p90 of single-step durations (ms), one event pair a step."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return [round(float(np.percentile(t, q)), 5) for q in (10, 50, 90)]
+
+
+_sweep = {}
+
+
+def cold_step_ms(fn, reps, torch, np):
+    """Median single-step duration (ms) with the L2 and the 256 MB Infinity
+    Cache evicted before every step by a read-only sweep of 1 GiB (a read
+    leaves no dirty lines to be written back inside the timed step)."""
+    if "buf" not in _sweep:
+        _sweep["buf"] = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    buf = _sweep["buf"]
+    t = []
+    for _ in range(reps):
+        _ = buf.sum()  # the read-only sweep
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        t.append(a.elapsed_time(b))
+    return float(np.median(t))
+
+
+def chained_copy_gbs(x, reps, torch):
+    """Read+write bandwidth (GB/s) of plain device copies of x's size chained
+    through three buffers (each copy reads what the previous one wrote, a
+    working set larger than the Infinity Cache, like the transform's chain)."""
+    bufs = [x.clone(), torch.empty_like(x), torch.empty_like(x)]
+    for i in range(3):
+        bufs[(i + 1) % 3].copy_(bufs[i % 3])
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for i in range(reps):
+        bufs[(i + 1) % 3].copy_(bufs[i % 3])
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    return 2 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9
+
+
 def kernel_name(p):
     """Device symbol (demangled, without the direction argument) of the
     kernel a pass descriptor launches."""
@@ -153,6 +204,9 @@ def headline(args, torch, np, mfft, inputs):
 
     level_ms = level_times_in_chain(plan, x, out, args.steps, torch)
     step_event_ms = time_events(lambda: plan.forward(x, out=out), args.steps, torch)
+    per_step = step_percentiles(lambda: plan.forward(x, out=out), args.steps, torch, np)
+    cold = cold_step_ms(lambda: plan.forward(x, out=out), max(5, args.steps // 5), torch, np)
+    copy_gbs = chained_copy_gbs(x, args.steps, torch)
     dom = int(np.argmax(level_ms))
     bytes_per_launch = 2 * 8 * n * batch  # read + write every element once
     achieved = bytes_per_launch / (level_ms[dom] * 1e-3) / 1e9
@@ -163,7 +217,9 @@ def headline(args, torch, np, mfft, inputs):
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": names[dom], "level": dom, "level_kernels": names,
                 "level_ms": [round(v, 5) for v in level_ms],
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "measured_copy_gbs": round(copy_gbs, 1),
+                "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
     result = {"metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1,
               "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -171,7 +227,9 @@ def headline(args, torch, np, mfft, inputs):
                                               "n": n, "batch": batch, "lift": lift},
               "roofline": roofline,
               "hbm_gbs_step": round(2 * bytes_per_launch / (ms_per_step * 1e-3) / 1e9, 1),
-              "event_ms_per_step": round(step_event_ms, 5)}
+              "event_ms_per_step": round(step_event_ms, 5),
+              "event_ms_per_step_p10_p50_p90": per_step,
+              "cold_ms_per_step_median": round(cold, 5)}
     sample = {"x": x_np, "y": out.cpu().numpy()}
     plan.close()
     return result, sample
@@ -208,7 +266,22 @@ def extras(args, torch, np, mfft, inputs):
             samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
                                        for i in pick]
         p.close()
+    # one plain launch per transform (8192 launches, timed once)
+    plans = {n: mfft.Plan(n, 1, None) for n in set(sizes)}
+    views = [xb[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+    outs = [ob[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+
+    def singles():
+        for i, s_ in enumerate(sizes):
+            plans[s_].forward(views[i], out=outs[i])
+    singles()
+    ms = time_events(singles, 1, torch)
+    rec["single_launches"] = {"ms": round(ms, 4), "launches": len(sizes),
+                              "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1)}
+    for q in plans.values():
+        q.close()
     rec["persistent_vs_per_size"] = round(rec["per_size"]["ms"] / rec["persistent"]["ms"], 3)
+    rec["persistent_vs_single_launches"] = round(rec["single_launches"]["ms"] / rec["persistent"]["ms"], 1)
     ex["uneven_batch_8192_2^6..2^14"] = rec
     del xb, ob
 

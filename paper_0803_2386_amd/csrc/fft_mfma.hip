@@ -255,10 +255,9 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
 
 // ---------------------------------------------------------------------------
 // Paired-column matrix-core level (LGN = 8 or 12).  The tile is the one of
-// the paired-column FP32 kernel -- 2^(15 - LGN) columns, each thread two
-// adjacent columns moved with 16-byte accesses on a unit-stride side -- so
-// the HBM traffic is the same; it runs on 512 threads with 32 points of each
-// column a thread, which leaves the registers the matrix-core stages need.  The radix-16 stages
+// the paired-column FP32 kernel -- 2^(15 - LGN) columns, 1024 threads, each
+// thread two adjacent columns x 16 points moved with 16-byte accesses on a
+// unit-stride side -- so the HBM traffic is the same.  The radix-16 stages
 // run on half of the tile at a time (the even columns, then the odd ones)
 // in LDS: the half is written to LDS in digit-reversed order, every stage
 // reads its B operands from LDS (twiddled and split), contracts them on the
@@ -326,7 +325,7 @@ __device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const floa
     constexpr int N = 1 << LGN;
     constexpr int NST = LGN / 4;
     constexpr int NB = N / 16;  // butterflies per column per stage
-    constexpr int GPW = 8;      // 16-butterfly groups per wave: 1024 butterflies, 8 waves
+    constexpr int GPW = 4;      // 16-butterfly groups per wave: 1024 butterflies, 16 waves
     const int lane = t & 63, wave = t >> 6, g = lane >> 4;
     union Op {
         V8 v;
@@ -390,15 +389,15 @@ __device__ __forceinline__ float2* mat(char* base, uint32_t off) { return reinte
 }  // namespace
 
 template <int LGN, int PREC, bool TIN, bool TOUT, bool FWD>
-__global__ void __launch_bounds__(512) k_pass_mfma_pair(PassArgs a)
+__global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
 {
     using V = float2;
     using Sp = SplitT<PREC>;
     using S = typename Sp::S;
     using V8 = typename Sp::V8;
     constexpr int N = 1 << LGN;
-    constexpr int E = 32;  // points of each column a thread
-    constexpr int LGTPC = LGN - 5, TPC = 1 << LGTPC;
+    constexpr int E = 16;  // points of each column a thread
+    constexpr int LGTPC = LGN - 4, TPC = 1 << LGTPC;
     constexpr int LGP = 14 - LGN, P = 1 << LGP;  // column pairs of the tile
     static_assert(LGN == 8 || LGN == 12, "paired-column matrix-core levels of 2^8 or 2^12 points");
 
@@ -412,14 +411,14 @@ __global__ void __launch_bounds__(512) k_pass_mfma_pair(PassArgs a)
     const int ui = TIN ? (t & (P - 1)) : (t >> LGTPC), ji = TIN ? (t >> LGP) : (t & (TPC - 1));
     const int uo = TOUT ? (t & (P - 1)) : (t >> LGTPC), jo = TOUT ? (t >> LGP) : (t & (TPC - 1));
 
-    V tab[4];
+    V tab[2];
     const int nt = 256 * (1 + a.tw_parts);
     {
         const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
         const V* g2 = reinterpret_cast<const V*>(a.tw_inter);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = t + 512 * k;
+        for (int k = 0; k < 2; ++k) {
+            const int i = t + 1024 * k;
             if (i < nt) tab[k] = i < 256 ? g1[i] : g2[i - 256];
         }
     }
@@ -452,8 +451,8 @@ __global__ void __launch_bounds__(512) k_pass_mfma_pair(PassArgs a)
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = t + 512 * k;
+    for (int k = 0; k < 2; ++k) {
+        const int i = t + 1024 * k;
         if (i < nt) tl[i] = tab[k];
     }
     V8 ahi[2], alo[2];
@@ -499,10 +498,10 @@ __global__ void __launch_bounds__(512) k_pass_mfma_pair(PassArgs a)
             const uint32_t dcol = uint32_t(d0) + 2u * uu + uint32_t(c);
             V f[E];
             f[0] = tw_inter32(tt, a.tw_parts, (dcol * ju) & mask);
-            V pw[5];
+            V pw[4];
 #pragma unroll
-            for (int b = 0; b < 5; ++b) pw[b] = tw_inter32(tt, a.tw_parts, (dcol * (uint32_t(TPC) << b)) & mask);
-            power_tree<5, false>(f, pw);
+            for (int b = 0; b < 4; ++b) pw[b] = tw_inter32(tt, a.tw_parts, (dcol * (uint32_t(TPC) << b)) & mask);
+            power_tree<4, false>(f, pw);
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = cmul_fwd_or_conj(v[m], f[m], FWD);
         }
@@ -542,7 +541,7 @@ static PassFn mfma_lookup(int lgn, int prec)
 #define MOA_MP(L, PR, F) \
     { {&k_pass_mfma_pair<L, PR, false, false, F>, &k_pass_mfma_pair<L, PR, false, true, F>}, \
       {&k_pass_mfma_pair<L, PR, true, false, F>, &k_pass_mfma_pair<L, PR, true, true, F>} }
-// [lgn 8 / 12][prec - 1][direction][tin][tout]; 512 threads
+// [lgn 8 / 12][prec - 1][direction][tin][tout]
 static const PassFn kMfmaPair[2][2][2][2][2] = {
     {{MOA_MP(8, 1, true), MOA_MP(8, 1, false)}, {MOA_MP(8, 2, true), MOA_MP(8, 2, false)}},
     {{MOA_MP(12, 1, true), MOA_MP(12, 1, false)}, {MOA_MP(12, 2, true), MOA_MP(12, 2, false)}},

@@ -179,7 +179,7 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     // below 2^32 bytes (32-bit lane offsets), at most 7 inter-level parts and
     // an inter-level root of at most 2^32 (32-bit exponents).
     // The split-precision matrix-core levels of 2^8 and 2^12 points use the
-    // same tile in a 512-thread kernel (fft_mfma.hip), with any sides.
+    // same tile in their own kernel (fft_mfma.hip), with any sides.
     auto pair_ok = [&](int lgw_) {
         if (fp64) return false;
         if (d.mfma ? (lgn != 8 && lgn != 12) : (lgn < 12 || lgn > 14 || !(in_tf || out_tf))) return false;
@@ -205,7 +205,7 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         d.data_elems = P * d.col_stride;
         d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * (d.tw ? d.tw_parts : 0)) * eb0;
         if (d.lds_bytes > moa::kLdsBytes) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
-        d.threads = d.mfma ? 512 : 1024;
+        d.threads = 1024;
         int64_t blocks = d.size[0] >> lgw_;
         for (int i = 1; i < d.nd; ++i) blocks *= d.size[i];
         if (blocks >= (int64_t(1) << 31)) return MOA_ERR_BATCH;

@@ -29,16 +29,15 @@ def check_pass(p, total, elem_bytes):
     pair = p["kernel_mode"] == 3
     E = min(N, p["points_per_thread"]) if not mfma else 1
     if pair:
-        # each thread owns two adjacent columns: 16 points of each (FP32
-        # kernel, 1024 threads) or 32 (matrix-core kernel, 512 threads)
-        E = 32 if mfma else 16
+        # each thread owns two adjacent columns, 16 points of each, on 1024 threads
+        E = 16
     TPC = N // E
     W = p["tile_width"]
     T = p["threads"]
     if pair:
         lgn = N.bit_length() - 1
         assert elem_bytes == 8 and W * N == 1 << 15
-        assert T == (W // 2) * TPC == (512 if mfma else 1024)
+        assert T == (W // 2) * TPC == 1024
         if mfma:
             assert lgn in (8, 12)
         else:
@@ -181,7 +180,7 @@ def test_mfma_pass_geometry(n, batch, lift, prec):
     d = _check_plan(h, n, batch, capi.MOA_C64)
     for p in d["passes"]:
         if p["mfma"] != "none":
-            per_thread = 64 if p["kernel_mode"] == 3 else 32
+            per_thread = 32
             assert p["threads"] % 64 == 0 and p["threads"] == p["tile_width"] * p["N"] // per_thread
 
 
