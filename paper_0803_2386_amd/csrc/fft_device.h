@@ -393,8 +393,8 @@ __device__ __forceinline__ void tile_offsets(const PassArgs& a, uint64_t tile_id
         rest = tile_id >> a.lg_tiles;
     }
     d0 = int64_t(tile << a.lgw);
-    ib = d0 * a.in_s[0];
-    ob = d0 * a.out_s[0];
+    ib = int64_t(tile) * a.in_tile_s;
+    ob = int64_t(tile) * a.out_tile_s;
     for (int d = 1; d < a.nd; ++d) {
         int64_t idx;
         if (d + 1 == a.nd) {

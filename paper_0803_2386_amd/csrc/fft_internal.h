@@ -10,6 +10,7 @@ namespace moa {
 constexpr int kMaxDigits = 8;     // batch digits of one pass descriptor
 constexpr int kMaxThreads = 512;  // level-kernel workgroup limit (1024: staged-store, paired-column and batch kernels)
 constexpr int kLdsBytes = 160 * 1024;
+constexpr int kNoBlock = 30;      // lgb of an axis with one plain stride
 constexpr int kMaxLgBlockC64 = 14;  // 2^14 complex64 = 128 KiB (+pad) in LDS
 constexpr int kMaxLgBlockC128 = 13; // 2^13 complex128
 
@@ -76,6 +77,14 @@ struct PassDesc {
     int xcd_remap = 0;
     int mfma = 0;                 // 0 = VALU radix-16, 1 = split bf16 MFMA, 2 = split fp16 MFMA
     int pre_lg = 0;               // log2 of the points transformed by earlier levels
+    // Blocked layouts (paired-column kernel only).  Row k of the DFT axis
+    // lies at (k mod 2^lgb) * s_e + (k >> lgb) * s_hi (lgb = kNoBlock: k * s_e);
+    // column w of tile t of digit 0 at t * tile_s + (w / 2) * pair_s +
+    // (w mod 2) * s[0].  The defaults make both plain strides.
+    int in_lgb = kNoBlock, out_lgb = kNoBlock;
+    int64_t in_s_hi = 0, out_s_hi = 0;
+    int64_t in_pair_s = 0, out_pair_s = 0;  // 0: 2 * s[0]
+    int64_t in_tile_s = 0, out_tile_s = 0;  // 0: tile width * s[0]
 };
 
 // Kernel argument block (passed by value).
@@ -99,6 +108,11 @@ struct PassArgs {
     int xcd_remap;
     int pre_lg;                   // log2 of the points transformed by earlier levels
     float sign;                   // -1 forward, +1 adjoint
+    // Blocked layouts (see PassDesc); the tile strides are always set.
+    int in_lgb, out_lgb;
+    int64_t in_s_hi, out_s_hi;
+    int64_t in_pair_s, out_pair_s;
+    int64_t in_tile_s, out_tile_s;
 };
 
 // A task of the uneven batch: `count` transforms of length 2^lgn whose

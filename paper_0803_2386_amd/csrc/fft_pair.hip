@@ -72,22 +72,27 @@ __device__ __forceinline__ void pair_tile(const PassArgs& a, uint64_t tile)
     const char* gin = reinterpret_cast<const char*>(a.in) + ib * int64_t(sizeof(V));
     char* gout = reinterpret_cast<char*>(a.out) + ob * int64_t(sizeof(V));
 
-    // 32-bit strides (bytes) and lane offsets; see at().
+    // 32-bit strides (bytes) and lane offsets; see at().  Row r of the DFT
+    // axis lies at (r mod 2^lgb) s_e + (r >> lgb) s_hi: with TPC a multiple
+    // of 2^lgb (planner), rows j + m TPC step by the uniform row(TPC).
+    auto row = [](uint32_t r, int lgb, uint32_t se, uint32_t shi) {
+        return (r & ((1u << lgb) - 1u)) * se + (r >> lgb) * shi;
+    };
     const uint32_t ju = uint32_t(j), uu = uint32_t(u);
     V v0[E], v1[E];
     {
-        const uint32_t se = uint32_t(a.in_s_e) * 8u, s0 = uint32_t(a.in_s[0]) * 8u;
-        const uint32_t step = uint32_t(TPC) * se;
+        const uint32_t se = uint32_t(a.in_s_e), shi = uint32_t(a.in_s_hi);
+        const uint32_t s0 = uint32_t(a.in_s[0]) * 8u;
+        const uint32_t step = row(uint32_t(TPC), a.in_lgb, se, shi) * 8u;
+        const uint32_t o0 = (uu * uint32_t(a.in_pair_s) + row(ju, a.in_lgb, se, shi)) * 8u;
         if constexpr (TIN) {
-            const uint32_t off = 16u * uu + ju * se;
 #pragma unroll
             for (int m = 0; m < E; ++m) {
-                const float4 x = *reinterpret_cast<const float4*>(at(gin, off + uint32_t(m) * step));
+                const float4 x = *reinterpret_cast<const float4*>(at(gin, o0 + uint32_t(m) * step));
                 v0[in_slot<LGN, 4>(m)] = make_float2(x.x, x.y);
                 v1[in_slot<LGN, 4>(m)] = make_float2(x.z, x.w);
             }
         } else {
-            const uint32_t o0 = 2u * uu * s0 + ju * se;
             const uint32_t o1 = o0 + s0;
 #pragma unroll
             for (int m = 0; m < E; ++m) {
@@ -120,17 +125,17 @@ __device__ __forceinline__ void pair_tile(const PassArgs& a, uint64_t tile)
         for (int m = 0; m < E; ++m) v[m] = cmul_dir<FWD>(v[m], f[out_slot_rank<LGN, 4>(m)]);
     };
 
-    const uint32_t sk = uint32_t(a.out_s_k) * 8u, s0 = uint32_t(a.out_s[0]) * 8u;
-    const uint32_t step = uint32_t(TPC) * sk;
+    const uint32_t sk = uint32_t(a.out_s_k), shi = uint32_t(a.out_s_hi), s0 = uint32_t(a.out_s[0]) * 8u;
+    const uint32_t step = row(uint32_t(TPC), a.out_lgb, sk, shi) * 8u;
+    const uint32_t o0 = (uu * uint32_t(a.out_pair_s) + row(ju, a.out_lgb, sk, shi)) * 8u;
     if constexpr (TOUT) {
         if (a.tw_parts) {
             twiddle(v0, 0);
             twiddle(v1, 1);
         }
-        const uint32_t off = 16u * uu + ju * sk;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            const uint32_t o = off + uint32_t(out_slot_rank<LGN, 4>(m)) * step;
+            const uint32_t o = o0 + uint32_t(out_slot_rank<LGN, 4>(m)) * step;
             *reinterpret_cast<float4*>(at(gout, o)) = make_float4(v0[m].x, v0[m].y, v1[m].x, v1[m].y);
         }
     } else {
@@ -139,7 +144,7 @@ __device__ __forceinline__ void pair_tile(const PassArgs& a, uint64_t tile)
         for (int c = 0; c < 2; ++c) {
             V* v = c ? v1 : v0;
             if (a.tw_parts) twiddle(v, c);
-            const uint32_t o = 2u * uu * s0 + ju * sk + uint32_t(c) * s0;
+            const uint32_t o = o0 + uint32_t(c) * s0;
 #pragma unroll
             for (int m = 0; m < E; ++m) *at(gout, o + uint32_t(out_slot_rank<LGN, 4>(m)) * step) = v[m];
         }

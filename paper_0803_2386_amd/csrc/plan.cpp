@@ -292,6 +292,42 @@ void push_digit(PassDesc& d, int64_t size, int64_t in_s, int64_t out_s)
 // from the PCT run lengths of D.  The last level writes the result through
 // the final transpose: X = (reverse iota L) transpose D, i.e. frequency digit
 // k_i lands at stride pi(take(i, f)).
+// Workspace layout of a two-level lift <f0 f1> whose levels both run the
+// paired-column kernel (column FFTs with 16-byte column-pair accesses, then
+// row FFTs with the final transpose).  The plain layout keeps D's digit
+// positions, so level 0 writes, and level 1 reads, 64-byte runs at a large
+// stride.  Instead, element (k0, c) of the workspace goes to
+//     (k0 >> b) B1 f1 + (c >> 1) 2 B1 + (k0 mod B1) 2 + (c mod 2),
+// B1 = 2^b = level 1's tile width: the reshape-transpose of Ch. 3 taken
+// blockwise, so that one level-0 tile writes, and one level-1 tile reads,
+// runs of 2 B1 W0 elements (512 bytes at <4096 4096>) while level 0 still
+// stores column pairs with 16-byte accesses.
+void pair_block_workspace(moa_fft_plan_s* p)
+{
+    if (p->passes.size() != 2 || p->fp64 || p->prec != MOA_FFT_PREC_NATIVE) return;
+    PassDesc& l0 = p->passes[0];
+    PassDesc& l1 = p->passes[1];
+    if (l0.kmode != 3 || l1.kmode != 3 || l0.mfma || l1.mfma) return;
+    if (!l0.in_tile_fast || !l0.out_tile_fast || l1.in_tile_fast || !l1.out_tile_fast) return;
+    const int64_t f1 = int64_t(1) << l1.lgn;
+    const int b = l1.lgw;                       // log2 B1
+    const int64_t B1 = int64_t(1) << b, W0 = int64_t(1) << l0.lgw;
+    if (l0.lgn - 4 < b) return;                 // rows j + m TPC must step blockwise
+    // Level 0 stores: column pair u of tile t at t W0 B1 + u 2 B1, row k0 blockwise.
+    l0.out_pair_s = 2 * B1;
+    l0.out_tile_s = W0 * B1;
+    l0.out_s_k = 2;
+    l0.out_lgb = b;
+    l0.out_s_hi = B1 * f1;
+    // Level 1 loads: column k0 = tile s, w at s B1 f1 + 2 w; row c as (c mod 2) + (c >> 1) 2 B1.
+    l1.in_s[0] = 2;
+    l1.in_pair_s = 4;
+    l1.in_tile_s = B1 * f1;
+    l1.in_s_e = 1;
+    l1.in_lgb = 1;
+    l1.in_s_hi = 2 * B1;
+}
+
 moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
 {
     const int L = int(p->levels.size());
@@ -334,6 +370,7 @@ moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         if (d.tw && !d.mfma && d.in_tile_fast != d.out_tile_fast) return MOA_ERR_STATE;
         p->passes.push_back(d);
     }
+    pair_block_workspace(p);
     return MOA_OK;
 }
 
@@ -462,7 +499,13 @@ std::string describe_json(const moa_fft_plan_s* p)
         for (int i = 0; i < d.nd; ++i)
             add("%s{\"size\":%lld,\"in_stride\":%lld,\"out_stride\":%lld}", i ? "," : "",
                 (long long)d.size[i], (long long)d.in_s[i], (long long)d.out_s[i]);
-        add("],\"twiddle_root\":%lld,\"twiddle_parts\":%d,\"grid\":%lld,\"tile_width\":%d,\"threads\":%d,\"blocks\":%lld,\"lds_bytes\":%d,"
+        add("],\"in_layout\":{\"block_lg\":%d,\"stride_hi\":%lld,\"pair_stride\":%lld,\"tile_stride\":%lld},"
+            "\"out_layout\":{\"block_lg\":%d,\"stride_hi\":%lld,\"pair_stride\":%lld,\"tile_stride\":%lld",
+            d.in_lgb, (long long)d.in_s_hi, (long long)(d.in_pair_s ? d.in_pair_s : 2 * d.in_s[0]),
+            (long long)(d.in_tile_s ? d.in_tile_s : (int64_t(1) << d.lgw) * d.in_s[0]), d.out_lgb, (long long)d.out_s_hi,
+            (long long)(d.out_pair_s ? d.out_pair_s : 2 * d.out_s[0]),
+            (long long)(d.out_tile_s ? d.out_tile_s : (int64_t(1) << d.lgw) * d.out_s[0]));
+        add("},\"twiddle_root\":%lld,\"twiddle_parts\":%d,\"grid\":%lld,\"tile_width\":%d,\"threads\":%d,\"blocks\":%lld,\"lds_bytes\":%d,"
             "\"lds_col_stride\":%d,\"in_tile_fast\":%s,\"out_tile_fast\":%s,\"xcd_remap\":%d,\"mfma\":\"%s\","
             "\"points_per_thread\":%d,\"kernel_mode\":%d}",
             d.tw ? (long long)(int64_t(1) << d.tw_lgroot) : 0LL, d.tw ? d.tw_parts : 0, (long long)d.grid, 1 << d.lgw,
@@ -524,6 +567,14 @@ void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, std:
         a.xcd_remap = d.xcd_remap;
         a.pre_lg = d.pre_lg;
         a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
+        a.in_lgb = d.in_lgb;
+        a.out_lgb = d.out_lgb;
+        a.in_s_hi = d.in_s_hi;
+        a.out_s_hi = d.out_s_hi;
+        a.in_pair_s = d.in_pair_s ? d.in_pair_s : 2 * d.in_s[0];
+        a.out_pair_s = d.out_pair_s ? d.out_pair_s : 2 * d.out_s[0];
+        a.in_tile_s = d.in_tile_s ? d.in_tile_s : (int64_t(1) << d.lgw) * d.in_s[0];
+        a.out_tile_s = d.out_tile_s ? d.out_tile_s : (int64_t(1) << d.lgw) * d.out_s[0];
         args.push_back(a);
     }
 }

@@ -23,6 +23,19 @@ def pad(i):
     return i + (i >> 4)
 
 
+def row_off(r, layout, stride):
+    """Offset of row r of a DFT axis: blockwise when the layout has a block."""
+    lg = layout["block_lg"]
+    if lg >= 30:
+        return r * stride
+    return (r & ((1 << lg) - 1)) * stride + (r >> lg) * layout["stride_hi"]
+
+
+def col_off(w, layout, stride0):
+    """Offset of column w inside a tile: pairs at pair_stride, stride0 within a pair."""
+    return (w >> 1) * layout["pair_stride"] + (w & 1) * stride0
+
+
 def check_pass(p, total, elem_bytes):
     N = p["N"]
     mfma = p["mfma"] != "none"
@@ -74,9 +87,10 @@ def check_pass(p, total, elem_bytes):
     else:
         lg_tiles = (axes[0]["size"] // W).bit_length() - 1
         tile, rest = bid & ((1 << lg_tiles) - 1), bid >> lg_tiles
-    d0 = tile * W
-    ib = d0 * axes[0]["in_stride"]
-    ob = d0 * axes[0]["out_stride"]
+    ib = tile * p["in_layout"]["tile_stride"]
+    ob = tile * p["out_layout"]["tile_stride"]
+    assert p["in_layout"]["tile_stride"] == W * axes[0]["in_stride"] or pair
+    assert p["out_layout"]["tile_stride"] == W * axes[0]["out_stride"] or pair
     for d in range(1, nd):
         if d == nd - 1:
             idx = rest
@@ -105,12 +119,14 @@ def check_pass(p, total, elem_bytes):
     m = np.arange(E)
     # loads: block x thread x slot
     rows = j[:, None] + m[None, :] * TPC
-    lane_in = (w * axes[0]["in_stride"])[:, None] + rows * p["dft_axis"]["in_stride"]
+    lane_in = (col_off(w, p["in_layout"], axes[0]["in_stride"])[:, None]
+               + row_off(rows, p["in_layout"], p["dft_axis"]["in_stride"]))
     load = ib[:, None, None] + lane_in[None, :, :]
     assert load.min() >= 0 and load.max() < total
     if pair:
         # 32-bit lane byte offsets, and 16-byte alignment on a unit-stride side
-        lane_out = (w * axes[0]["out_stride"])[:, None] + rows * p["dft_axis"]["out_stride"]
+        lane_out = (col_off(w, p["out_layout"], axes[0]["out_stride"])[:, None]
+                    + row_off(rows, p["out_layout"], p["dft_axis"]["out_stride"]))
         assert lane_in.max() * 8 < 1 << 32 and lane_out.max() * 8 < 1 << 32
         even = slice(0, T)
         if p["in_tile_fast"]:
@@ -122,8 +138,8 @@ def check_pass(p, total, elem_bytes):
     # stores: every (column, k) of every block
     k = np.arange(N)
     ww = np.arange(W)
-    store = (ob[:, None, None] + (ww * axes[0]["out_stride"])[None, :, None]
-             + k[None, None, :] * p["dft_axis"]["out_stride"])
+    store = (ob[:, None, None] + col_off(ww, p["out_layout"], axes[0]["out_stride"])[None, :, None]
+             + row_off(k, p["out_layout"], p["dft_axis"]["out_stride"])[None, None, :])
     assert store.min() >= 0 and store.max() < total
     flat = np.sort(store.ravel())
     assert flat.size == total and np.array_equal(flat, np.arange(total)), "outputs not a permutation"
