@@ -239,11 +239,14 @@ def extras(args, torch, np, mfft, inputs):
     """Other workloads, timed the same way (context for the headline line).
     Returns the records and, per record, host copies of a few transforms for
     the error statement of the CPU leg."""
+    from paper_0803_2386_amd import tune
     ex, samples = {}, {}
     dev = torch.device("cuda", 0)
     reps = max(5, args.steps // 2)
 
-    # Uneven batch: one persistent launch vs one plain launch per size.
+    # Uneven batch: one fused launch (default grid: one workgroup per task;
+    # resident grid: persistent, two workgroups per CU) vs one plain launch
+    # per size, and the fused launch replayed from a HIP graph.
     sizes = [int(s) for s in inputs.uneven_sizes(8192, 6, 14, seed=args.seed)]
     total = sum(sizes)
     offs = np.concatenate([[0], np.cumsum(sizes)])
@@ -252,20 +255,32 @@ def extras(args, torch, np, mfft, inputs):
     ob = torch.empty_like(xb)
     rec = {"transforms": len(sizes), "elements": total}
     pick = [0, int(np.argmax(sizes)), len(sizes) - 1]
-    for name, kw in (("persistent", {}), ("per_size", {"per_size": True}),
-                     ("persistent_graph", {"graph": True})):
+    probe = mfft.BatchedPlan(sizes, host_only=True)
+    d = probe.describe()
+    probe.close()
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    resident = cus * max(1, (160 * 1024) // d["lds_bytes"])
+    rec["tasks"] = d["tasks"]
+
+    def entry(ms, p):
+        return {"ms": round(ms, 5), "grid": p.describe()["persistent_blocks"],
+                "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1),
+                "frac_hbm_peak": round(16 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    for name, kw in (("one_launch", {}), ("resident_grid", {"tuning": {"persistent_blocks": resident}}),
+                     ("per_size", {"per_size": True}), ("graph", {"graph": True})):
         p = mfft.BatchedPlan(sizes, **kw)
         for _ in range(3):
             p.forward(xb, out=ob)
         ms = time_events(lambda: p.forward(xb, out=ob), reps, torch)
-        rec[name] = {"ms": round(ms, 5), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
-                     "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1),
-                     "frac_hbm_peak": round(16 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        if name == "persistent_graph":
+        rec[name] = entry(ms, p)
+        if name == "graph":
             xs, ys = xb.cpu().numpy(), ob.cpu().numpy()
             samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
                                        for i in pick]
         p.close()
+    best = tune.tune_batched(sizes, grids=(0, resident // 2, resident, 2 * resident))
+    rec["tuned"] = {"ms": round(best["ms"], 5), "grid": best["grid"]}
     # one plain launch per transform (8192 launches, timed once)
     plans = {n: mfft.Plan(n, 1, None) for n in set(sizes)}
     views = [xb[offs[i]:offs[i + 1]] for i in range(len(sizes))]
@@ -280,8 +295,8 @@ def extras(args, torch, np, mfft, inputs):
                               "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1)}
     for q in plans.values():
         q.close()
-    rec["persistent_vs_per_size"] = round(rec["per_size"]["ms"] / rec["persistent"]["ms"], 3)
-    rec["persistent_vs_single_launches"] = round(rec["single_launches"]["ms"] / rec["persistent"]["ms"], 1)
+    rec["one_launch_vs_per_size"] = round(rec["per_size"]["ms"] / rec["one_launch"]["ms"], 3)
+    rec["one_launch_vs_single_launches"] = round(rec["single_launches"]["ms"] / rec["one_launch"]["ms"], 1)
     ex["uneven_batch_8192_2^6..2^14"] = rec
     del xb, ob
 
@@ -335,7 +350,6 @@ def extras(args, torch, np, mfft, inputs):
     del xm, ym
 
     # The autotuner's lift and tile widths for n = 2^24 (up to three levels).
-    from paper_0803_2386_amd import tune
     with tempfile.TemporaryDirectory() as td:
         os.environ["MOA_FFT_TUNE_CACHE"] = os.path.join(td, "tune.json")
         best = tune.tune(1 << 24, 1, max_levels=3, reps=5, use_cache=False)

@@ -81,7 +81,7 @@ typedef enum {
                                          returns MOA_ERR_STATE              */
 #define MOA_FFT_FLAG_PER_SIZE 0x2u    /* uneven batch: one plain launch per
                                          distinct size instead of one
-                                         persistent launch                  */
+                                         fused launch                       */
 #define MOA_FFT_FLAG_GRAPH 0x4u       /* record the plan's launches for each
                                          (direction, in, out) once as a HIP
                                          graph of kernel nodes and replay it
@@ -92,9 +92,10 @@ typedef enum {
 typedef struct {
     int32_t cols_per_block[8];  /* transforms (columns of the lifted view)
                                    handled by one workgroup in that pass   */
-    int32_t persistent_blocks;  /* uneven batch: workgroups of the
-                                   persistent launch (0 = one per task up
-                                   to the device's resident limit)          */
+    int32_t persistent_blocks;  /* uneven batch: workgroups of the fused
+                                   launch (0 = one per task; fewer make it
+                                   persistent, each workgroup walking the
+                                   tasks with a grid stride)               */
     int32_t reserved[7];
 } moa_fft_tuning_t;
 
@@ -132,8 +133,10 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch,
  * (each a power of two between 1 and 2^14 for MOA_C64, 2^13 for MOA_C128),
  * packed one after the other in input and output (transform i starts at
  * element sum_{j<i} sizes[j]).  The host array `sizes` is copied.  By
- * default all transforms run in one persistent launch; with
- * MOA_FFT_FLAG_PER_SIZE they run as one plain launch per distinct size.
+ * default all transforms run in one fused launch of one workgroup per task
+ * (tasks ordered longest first; a tuned smaller grid makes the launch
+ * persistent); with MOA_FFT_FLAG_PER_SIZE they run as one plain launch per
+ * distinct size.
  * Errors as moa_fft_plan; MOA_ERR_SIZE names an invalid entry of sizes.
  */
 moa_status_t moa_fft_plan_batched(moa_fft_plan_t* out, const int64_t* sizes, int64_t count,
@@ -162,14 +165,14 @@ moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, v
  * ("The General Algorithm": one level = one pass over memory).  For an
  * uneven batch planned with MOA_FFT_FLAG_PER_SIZE, level g runs the
  * transforms of the g-th distinct length (longest first) from `in` to `out`;
- * for the persistent form level 0 is the whole launch.  Errors as
+ * for the fused form level 0 is the whole launch.  Errors as
  * moa_fft_exec, plus MOA_ERR_ARG for a level outside 0..L-1.
  */
 moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t level, const void* in,
                                 void* out, void* stream);
 
 /* Number of levels (= kernel launches per execution) of a plan; 1 for an
- * uneven batch in one persistent launch, the number of distinct lengths for
+ * uneven batch in one fused launch, the number of distinct lengths for
  * one planned with MOA_FFT_FLAG_PER_SIZE. */
 moa_status_t moa_fft_num_levels(moa_fft_plan_t p, int32_t* levels);
 

@@ -1,10 +1,12 @@
 // Uneven batch: thousands of independent transforms of power-of-two lengths
-// (2^0 .. 2^14 points) in one persistent launch.
+// (2^0 .. 2^14 points) in one fused launch.
 //
 // The host groups transforms of equal length into tasks that fill one
 // workgroup (up to 2^14 points, several short transforms side by side as the
-// columns of the LDS exchange tile) and orders the tasks longest first; each
-// resident workgroup walks the task list with a grid stride.  A task is one
+// columns of the LDS exchange tile) and orders the tasks longest first.  By
+// default the grid has one workgroup per task and the dispatcher hands out
+// the tasks in that order; with a smaller grid each workgroup walks the task
+// list with a grid stride (persistent form).  A task is one
 // level of the method (Ch. 3): every butterfly of every transform in it runs
 // inside the workgroup (VGPRs and LDS), so each element crosses HBM exactly
 // once in each direction.
@@ -84,13 +86,30 @@ __device__ __forceinline__ void task_run(typename cpx<R>::V (&v)[kTaskPts], type
         default: break;            \
     }
 
+// The in-block twiddle table (kTwBlkEntries <= 512 entries, one a thread):
+// each thread loads its entry once, ahead of any data, and every task stores
+// it to LDS after issuing its data loads, so a workgroup's first task waits
+// for one memory round trip instead of two.  The stages read the table only
+// behind their first exchange barrier, which publishes it.
+// Complex128 stores the table up front instead: the per-task store costs that
+// kernel its register-resident task array (the compiler moves it to scratch).
+template <typename R>
+constexpr bool kTableWithTask = sizeof(R) == 4;
+
+template <typename V>
+__device__ __forceinline__ void store_table(V* tl, const V& tab, int t)
+{
+    if (t < kTwBlkEntries) tl[t] = tab;
+}
+
 // One 2^14-point complex64 transform at element offset `off` (512 threads):
 // e = its even samples, o = its odd samples, 16 points of each a thread,
 // transformed together as the two columns of a paired tile (their exchanges
 // take turns in the one LDS column), then
 // X[k] = E[k] + w^k O[k], X[k + 2^13] = E[k] - w^k O[k], w = omega_{2^14}.
 template <bool FWD>
-__device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, float2* lds, const float2* tl, int t)
+__device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, float2* lds, float2* tl,
+                                            const float2& tab, int t)
 {
     using V = float2;
     constexpr int LGH = 13, TPC = 512, E = 16;
@@ -103,6 +122,7 @@ __device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, flo
         e[in_slot<LGH, 4>(m)] = src[i];
         o[in_slot<LGH, 4>(m)] = src[i + 1];
     }
+    store_table(tl, tab, t);
     pair_stages<FWD, LGH, 0>(e, o, lds, t, tl);
     // w^k for k = t + rank * TPC: base w^t times the powers w^(TPC 2^b) of
     // the set bits b of rank.
@@ -123,9 +143,12 @@ __device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, flo
 // The run of this workgroup's tasks (ti, ti + G, ...) that hold transforms
 // of 2^LGN points; returns the first task of the run's end.  The
 // longest-first task order makes each workgroup's walk a few such runs.
+// No register prefetch of the next task: the second resident workgroup of
+// the CU overlaps this one's memory phases, and the registers a prefetch
+// would need are what let two workgroups fit.
 template <typename R, bool FWD, int LGN>
 __device__ __forceinline__ int batch_run(const BatchArgs& a, int ti, typename cpx<R>::V* lds,
-                                         const typename cpx<R>::V* tl, int t)
+                                         typename cpx<R>::V* tl, const typename cpx<R>::V& tab, int t)
 {
     using V = typename cpx<R>::V;
     constexpr int LGE = task_lge<R, LGN>();
@@ -137,58 +160,35 @@ __device__ __forceinline__ int batch_run(const BatchArgs& a, int ti, typename cp
     if constexpr (LGN == 14 && sizeof(R) == 4) {
         for (; same(ti); ti += G) {
             asm volatile("" : "+v"(tt));
-            split14_run<FWD>(a, a.toff[a.tasks[ti].first], lds, tl, tt);
+            split14_run<FWD>(a, a.toff[a.tasks[ti].first], lds, tl, tab, tt);
             __syncthreads();  // the next task overwrites the LDS exchange area
         }
         return ti;
     } else {
-        // No register prefetch: the second resident workgroup of the CU
-        // overlaps this one's memory phases, and the registers it would need
-        // are what let two workgroups fit.
-        constexpr bool kPF = false;
         const V* __restrict__ in = reinterpret_cast<const V*>(a.in);
         V* __restrict__ out = reinterpret_cast<V*>(a.out);
-        auto fetch = [&](int task, V (&dst)[kTaskPts], int64_t& o, bool& act) {
-            const BatchTask tk = a.tasks[task];
-            const int w = t >> LGTPC;
-            act = w < tk.count;
-            o = act ? a.toff[tk.first + w] : 0;
-            if (act) task_load<R, LGN>(dst, in, o, t);
-        };
         V v[kTaskPts];
-        int64_t off = 0;
-        bool active = false;
-        if (kPF) fetch(ti, v, off, active);
         for (; same(ti); ti += G) {
             // Keep the stage addresses (all derived from the thread index) out
             // of reach of loop-invariant code motion, which would hold them in
-            // VGPRs.
+            // VGPRs (and spill them) across every size's loop.
             asm volatile("" : "+v"(tt));
-            V vn[kTaskPts];
-            int64_t noff = 0;
-            bool nact = false;
-            const bool more = same(ti + G);
-            if (kPF) {
-                if (more) fetch(ti + G, vn, noff, nact);
-            } else {
-                fetch(ti, v, off, active);
-            }
+            const BatchTask tk = a.tasks[ti];
+            const int w = tt >> LGTPC;
+            const bool active = w < tk.count;
+            const int64_t off = active ? a.toff[tk.first + w] : 0;
+            if (active) task_load<R, LGN>(v, in, off, tt);
+            if constexpr (kTableWithTask<R>) store_table(tl, tab, tt);
             task_run<R, LGN>(v, out, off, active, lds, tl, R(a.sign), tt);
             __syncthreads();  // the next task overwrites the LDS exchange area
-            if (kPF && more) {
-#pragma unroll
-                for (int m = 0; m < (1 << lg_e(LGN, LGE)); ++m) v[m] = vn[m];
-                off = noff;
-                active = nact;
-            }
         }
         return ti;
     }
 }
 
-// Persistent uneven batch: each workgroup walks the tasks blockIdx.x,
-// blockIdx.x + G, ... as runs of equal transform length; two workgroups are
-// resident on each CU (complex64).
+// Uneven batch: each workgroup runs the tasks blockIdx.x, blockIdx.x + G, ...
+// (one task when the grid has one workgroup per task) as runs of equal
+// transform length; two workgroups are resident on each CU (complex64).
 template <typename R, bool FWD>
 __global__ void __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) k_batched(BatchArgs a)
 {
@@ -197,19 +197,21 @@ __global__ void __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) k_batched(BatchAr
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
     V* tl = lds + a.data_elems;
-    const int t = threadIdx.x, T = blockDim.x;
+    static_assert(kTwBlkEntries <= 512, "one table entry a thread");
+    const int t = threadIdx.x;
     const int end = a.task0 + a.ntasks;
-    {
-        const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
-        for (int i = t; i < kTwBlkEntries; i += T) tl[i] = g1[i];
+    V tab{};
+    if (t < kTwBlkEntries) tab = reinterpret_cast<const V*>(a.tw_blk)[t];
+    if constexpr (!kTableWithTask<R>) {
+        store_table(tl, tab, t);
+        __syncthreads();
     }
-    __syncthreads();
     int ti = a.task0 + int(blockIdx.x);
     while (ti < end) {
         const int lgn = a.tasks[ti].lgn;
         int nti = end;
 #define MOA_RUN(L) \
-    if constexpr (L <= kMaxLg) nti = batch_run<R, FWD, L>(a, ti, lds, tl, t)
+    if constexpr (L <= kMaxLg) nti = batch_run<R, FWD, L>(a, ti, lds, tl, tab, t)
         MOA_TASK_SWITCH(lgn, MOA_RUN)
 #undef MOA_RUN
         ti = nti;

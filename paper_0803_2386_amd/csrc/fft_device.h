@@ -362,8 +362,15 @@ __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V*
             }
         }
         if constexpr (S + 1 < NST) {
-            if (active) load_stage_twiddles<R, LGN, LGE, S + 1>(tw, j, sign, twb);
-            if constexpr (READS_LDS) __syncthreads();
+            // After a stage read from LDS the next stage's factors load while
+            // the barrier drains; after the register-only first stage they
+            // load behind the exchange barrier, which also publishes a table
+            // stored just before the stages (a batched task stores it with
+            // its data loads in flight).
+            if constexpr (READS_LDS) {
+                if (active) load_stage_twiddles<R, LGN, LGE, S + 1>(tw, j, sign, twb);
+                __syncthreads();
+            }
             if (active) {
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
@@ -374,6 +381,9 @@ __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V*
                 }
             }
             __syncthreads();
+            if constexpr (!READS_LDS) {
+                if (active) load_stage_twiddles<R, LGN, LGE, S + 1>(tw, j, sign, twb);
+            }
             run_stages<R, LGN, LGE, S + 1, FROM_LDS>(v, col, j, sign, twb, active, tw);
         }
     }

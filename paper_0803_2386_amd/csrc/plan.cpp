@@ -730,18 +730,15 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     p->batch_data_elems = int(lds_max / int64_t(eb));
     p->batch_lds = lds_max + moa::kTwBlkEntries * int(eb);
     if (p->batch_lds > moa::kLdsBytes) return MOA_ERR_STATE;
+    // Default grid: one workgroup per task.  The hardware dispatcher then
+    // hands each freed slot the next task of the longest-first order, which
+    // balances the CUs better than any static split of tasks this coarse
+    // (at 8192 mixed transforms a 2^14-point task is over a quarter of what
+    // each of the 512 resident workgroups moves).  A tuned grid smaller than that makes the launch
+    // persistent: each workgroup walks tasks blockIdx.x, + grid, ...
     int grid = int(p->tasks.size());
     if (tuning && tuning->persistent_blocks < 0) return MOA_ERR_TUNING;
-    if (tuning && tuning->persistent_blocks > 0) {
-        grid = std::min(grid, int(tuning->persistent_blocks));
-    } else if (!p->host_only) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const int per_cu = std::max(1, moa::kLdsBytes / p->batch_lds);
-        grid = std::min(grid, cus * per_cu);
-    } else {
-        grid = std::min(grid, 256 * std::max(1, moa::kLdsBytes / p->batch_lds));
-    }
+    if (tuning && tuning->persistent_blocks > 0) grid = std::min(grid, int(tuning->persistent_blocks));
     p->batch_grid = std::max(grid, 1);
     return MOA_OK;
 }
@@ -925,7 +922,7 @@ moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t lev
     if (p->host_only && !p->batched && level >= 0 && size_t(level) < p->passes.size()) return MOA_ERR_STATE;
     if (p->batched) {
         // An uneven batch: level = one size group of a per-size plan, or the
-        // single persistent launch (level 0).
+        // single fused launch (level 0).
         const bool per_size = (p->flags & MOA_FFT_FLAG_PER_SIZE) != 0;
         const int groups = per_size ? int(p->size_ranges.size()) : 1;
         if (level < 0 || level >= groups) return MOA_ERR_ARG;

@@ -133,7 +133,7 @@ class Plan(_PlanBase):
 class BatchedPlan(_PlanBase):
     """Uneven batch: transform i has length sizes[i] (a power of two) and the
     transforms are packed one after the other.  ``per_size`` runs one plain
-    launch per distinct size instead of the single persistent launch."""
+    launch per distinct size instead of the single fused launch."""
 
     def __init__(self, sizes: Sequence[int], dtype: torch.dtype = torch.complex64, per_size: bool = False,
                  graph: bool = False, tuning: Optional[dict] = None, device: Optional[torch.device] = None,

@@ -1,5 +1,5 @@
 """Autotuner: picks the lift and the per-level tile widths of a plan by timing
-candidates on the device, and the persistent grid of an uneven batch.
+candidates on the device, and the grid of an uneven batch's fused launch.
 
 The paper leaves the blocking size c as a run-time parameter to be chosen per
 machine (Ch. 1 and Ch. 3, "Results and Discussion": the best c was found by
@@ -166,7 +166,9 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
 
 def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 128, 256, 384, 512, 768, 1024),
                  reps: int = 10, verbose: bool = False) -> dict:
-    """Time the persistent grid of an uneven batch; returns the best tuning."""
+    """Time grids of an uneven batch's fused launch (0 = one workgroup per
+    task, the default; smaller grids make it persistent); returns the best
+    tuning."""
     import torch
 
     from . import fft as mfft
