@@ -116,18 +116,27 @@ def cold_step_ms(fn, reps, torch, np):
 def chained_copy_gbs(x, reps, torch):
     """Read+write bandwidth (GB/s) of plain device copies of x's size chained
     through three buffers (each copy reads what the previous one wrote, a
-    working set larger than the Infinity Cache, like the transform's chain)."""
+    working set larger than the Infinity Cache, like the transform's chain).
+    The best of torch's device-to-device copy and an elementwise pass over a
+    float32 view (multiply by one, which streams 16 bytes a lane and runs
+    about 40% faster than the copy on MI355X)."""
     bufs = [x.clone(), torch.empty_like(x), torch.empty_like(x)]
-    for i in range(3):
-        bufs[(i + 1) % 3].copy_(bufs[i % 3])
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for i in range(reps):
-        bufs[(i + 1) % 3].copy_(bufs[i % 3])
-    e.record()
-    e.synchronize()
-    ms = s.elapsed_time(e) / reps
-    return 2 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9
+    flt = [b.view(torch.float32) for b in bufs]
+    ops = (lambda i: bufs[(i + 1) % 3].copy_(bufs[i % 3]),
+           lambda i: torch.mul(flt[i % 3], 1.0, out=flt[(i + 1) % 3]))
+    best = 0.0
+    for op in ops:
+        for i in range(3):
+            op(i)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for i in range(reps):
+            op(i)
+        e.record()
+        e.synchronize()
+        ms = s.elapsed_time(e) / reps
+        best = max(best, 2 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9)
+    return best
 
 
 def kernel_name(p):
