@@ -284,9 +284,31 @@ def test_batched_plan_partitions_the_transforms():
     assert d["lds_bytes"] <= 160 * 1024 and d["threads"] == 512
 
 
+def test_batched_grid_defaults_to_one_workgroup_per_task():
+    """The fused launch has one workgroup per task unless a tuned grid caps it
+    (then each workgroup walks the tasks with a grid stride); a negative grid
+    is rejected."""
+    sizes = [64, 128, 64, 16384, 8, 8192, 8192, 1, 64] * 40
+
+    def grid(tuning):
+        h = capi.moa_fft_plan_batched(sizes, flags=HOST, tuning=tuning)
+        try:
+            d = json.loads(capi.moa_fft_describe(h))
+        finally:
+            capi.moa_fft_destroy(h)
+        return d["persistent_blocks"], d["tasks"]
+
+    g, tasks = grid(None)
+    assert g == tasks
+    assert grid({"persistent_blocks": 7}) == (7, tasks)
+    assert grid({"persistent_blocks": 10 * tasks}) == (tasks, tasks)
+    assert status_of(capi.moa_fft_plan_batched, sizes, flags=HOST,
+                     tuning={"persistent_blocks": -1}) == capi.MOA_ERR_TUNING
+
+
 def test_batched_exec_level_validation():
     """exec_level on an uneven batch: host-only plans cannot run, levels are
-    the size groups of a per-size plan (one level for the persistent form)."""
+    the size groups of a per-size plan (one level for the fused form)."""
     sizes = [64, 4096, 64, 16384, 1]
     for flags, groups in ((capi.MOA_FFT_FLAG_PER_SIZE, 4), (0, 1)):
         h = capi.moa_fft_plan_batched(sizes, flags=HOST | flags)

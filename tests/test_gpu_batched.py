@@ -1,5 +1,6 @@
-"""GPU parity of the uneven batch (one persistent launch, per-size launches,
-graph replay) against the FP64 oracle, per transform."""
+"""GPU parity of the uneven batch (one fused launch with one workgroup per
+task or a smaller persistent grid, per-size launches, graph replay) against
+the FP64 oracle, per transform."""
 import numpy as np
 import pytest
 
