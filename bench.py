@@ -8,6 +8,7 @@ transpose folded into the store).  A step is one full transform; inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
+                    [--extras uneven,fwd_adj,split_mfma,tuned,c128]
 
 Throughput is 5 n log2(n) / t (GFLOP/s).  The roofline block reports the
 dominant kernel (the slower of the two level launches, each timed in its place
@@ -252,128 +253,137 @@ def extras(args, torch, np, mfft, inputs):
     ex, samples = {}, {}
     dev = torch.device("cuda", 0)
     reps = max(5, args.steps // 2)
+    chosen = set(args.extras.split(","))
 
-    # Uneven batch: one fused launch (default grid: one workgroup per task;
-    # resident grid: persistent, two workgroups per CU) vs one plain launch
-    # per size, and the fused launch replayed from a HIP graph.
-    sizes = [int(s) for s in inputs.uneven_sizes(8192, 6, 14, seed=args.seed)]
-    total = sum(sizes)
-    offs = np.concatenate([[0], np.cumsum(sizes)])
-    flops = sum(5.0 * s * math.log2(s) for s in sizes)
-    xb = inputs.device_uniform_complex(total, args.seed, torch.complex64, dev)
-    ob = torch.empty_like(xb)
-    rec = {"transforms": len(sizes), "elements": total}
-    pick = [0, int(np.argmax(sizes)), len(sizes) - 1]
-    probe = mfft.BatchedPlan(sizes, host_only=True)
-    d = probe.describe()
-    probe.close()
-    cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    resident = cus * max(1, (160 * 1024) // d["lds_bytes"])
-    rec["tasks"] = d["tasks"]
+    def want(name):
+        return "all" in chosen or name in chosen
 
-    def entry(ms, p):
-        return {"ms": round(ms, 5), "grid": p.describe()["persistent_blocks"],
-                "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
-                "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1),
-                "frac_hbm_peak": round(16 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    for name, kw in (("one_launch", {}), ("resident_grid", {"tuning": {"persistent_blocks": resident}}),
-                     ("per_size", {"per_size": True}), ("graph", {"graph": True})):
-        p = mfft.BatchedPlan(sizes, **kw)
-        for _ in range(3):
-            p.forward(xb, out=ob)
-        ms = time_events(lambda: p.forward(xb, out=ob), reps, torch)
-        rec[name] = entry(ms, p)
-        if name == "graph":
-            xs, ys = xb.cpu().numpy(), ob.cpu().numpy()
-            samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
-                                       for i in pick]
+    if want("uneven"):
+        # Uneven batch: one fused launch (default grid: one workgroup per task;
+        # resident grid: persistent, two workgroups per CU) vs one plain launch
+        # per size, and the fused launch replayed from a HIP graph.
+        sizes = [int(s) for s in inputs.uneven_sizes(8192, 6, 14, seed=args.seed)]
+        total = sum(sizes)
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        flops = sum(5.0 * s * math.log2(s) for s in sizes)
+        xb = inputs.device_uniform_complex(total, args.seed, torch.complex64, dev)
+        ob = torch.empty_like(xb)
+        rec = {"transforms": len(sizes), "elements": total}
+        pick = [0, int(np.argmax(sizes)), len(sizes) - 1]
+        probe = mfft.BatchedPlan(sizes, host_only=True)
+        d = probe.describe()
+        probe.close()
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        resident = cus * max(1, (160 * 1024) // d["lds_bytes"])
+        rec["tasks"] = d["tasks"]
+
+        def entry(ms, p):
+            return {"ms": round(ms, 5), "grid": p.describe()["persistent_blocks"],
+                    "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                    "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1),
+                    "frac_hbm_peak": round(16 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        for name, kw in (("one_launch", {}), ("resident_grid", {"tuning": {"persistent_blocks": resident}}),
+                         ("per_size", {"per_size": True}), ("graph", {"graph": True})):
+            p = mfft.BatchedPlan(sizes, **kw)
+            for _ in range(3):
+                p.forward(xb, out=ob)
+            ms = time_events(lambda: p.forward(xb, out=ob), reps, torch)
+            rec[name] = entry(ms, p)
+            if name == "graph":
+                xs, ys = xb.cpu().numpy(), ob.cpu().numpy()
+                samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
+                                           for i in pick]
+            p.close()
+        best = tune.tune_batched(sizes, grids=(0, resident // 2, resident, 2 * resident))
+        rec["tuned"] = {"ms": round(best["ms"], 5), "grid": best["grid"]}
+        # one plain launch per transform (8192 launches, timed once)
+        plans = {n: mfft.Plan(n, 1, None) for n in set(sizes)}
+        views = [xb[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+        outs = [ob[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+
+        def singles():
+            for i, s_ in enumerate(sizes):
+                plans[s_].forward(views[i], out=outs[i])
+        singles()
+        ms = time_events(singles, 1, torch)
+        rec["single_launches"] = {"ms": round(ms, 4), "launches": len(sizes),
+                                  "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1)}
+        for q in plans.values():
+            q.close()
+        rec["one_launch_vs_per_size"] = round(rec["per_size"]["ms"] / rec["one_launch"]["ms"], 3)
+        rec["one_launch_vs_single_launches"] = round(rec["single_launches"]["ms"] / rec["one_launch"]["ms"], 1)
+        ex["uneven_batch_8192_2^6..2^14"] = rec
+        del xb, ob
+
+    if want("fwd_adj"):
+        # Differentiable workload: forward + adjoint, 256 x 2^16, lift <256 256>.
+        n, B = 1 << 16, 256
+        p = mfft.Plan(n, B, [256, 256])
+        xa = inputs.device_uniform_complex(n * B, args.seed + 1, torch.complex64, dev)
+        ya = torch.empty_like(xa)
+        za = torch.empty_like(xa)
+
+        def fwd_adj():
+            p.forward(xa, out=ya)
+            p.adjoint(ya, out=za)
+        fwd_adj()
+        ms = time_events(fwd_adj, reps, torch)
+        ex["fwd_adj_b256_2^16"] = {"ms": round(ms, 5), "gflops": round(2 * gflops(n, B, ms * 1e-3), 1),
+                                   "hbm_gbs": round(4 * 16 * n * B / (ms * 1e-3) / 1e9, 1)}
         p.close()
-    best = tune.tune_batched(sizes, grids=(0, resident // 2, resident, 2 * resident))
-    rec["tuned"] = {"ms": round(best["ms"], 5), "grid": best["grid"]}
-    # one plain launch per transform (8192 launches, timed once)
-    plans = {n: mfft.Plan(n, 1, None) for n in set(sizes)}
-    views = [xb[offs[i]:offs[i + 1]] for i in range(len(sizes))]
-    outs = [ob[offs[i]:offs[i + 1]] for i in range(len(sizes))]
+        del xa, ya, za
 
-    def singles():
-        for i, s_ in enumerate(sizes):
-            plans[s_].forward(views[i], out=outs[i])
-    singles()
-    ms = time_events(singles, 1, torch)
-    rec["single_launches"] = {"ms": round(ms, 4), "launches": len(sizes),
-                              "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1)}
-    for q in plans.values():
-        q.close()
-    rec["one_launch_vs_per_size"] = round(rec["per_size"]["ms"] / rec["one_launch"]["ms"], 3)
-    rec["one_launch_vs_single_launches"] = round(rec["single_launches"]["ms"] / rec["one_launch"]["ms"], 1)
-    ex["uneven_batch_8192_2^6..2^14"] = rec
-    del xb, ob
+    if want("split_mfma"):
+        # Split-precision matrix-core levels vs FP32, 256 x 2^20, lift <256 4096>.
+        n, B, lift = 1 << 20, 256, [256, 4096]
+        xm = inputs.device_uniform_complex(n * B, args.seed + 3, torch.complex64, dev)
+        ym = torch.empty_like(xm)
+        rows = [0, B - 1]
+        xs = xm.view(B, n)[rows].cpu().numpy()
+        rec = {"lift": lift}
+        for prec in ("native", "split_bf16", "split_fp16"):
+            p = mfft.Plan(n, B, lift, prec=prec)
+            d = p.describe()
+            p.forward(xm, out=ym)
+            mreps = max(3, reps // 2)
+            ms = time_events(lambda: p.forward(xm, out=ym), mreps, torch)
+            lv = level_times_in_chain(p, xm, ym, mreps, torch)
+            levels = len(d["passes"])
+            r = {"ms": round(ms, 4), "gflops": round(gflops(n, B, ms * 1e-3), 1),
+                 "hbm_gbs": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9, 1),
+                 "level_ms": [round(v, 4) for v in lv], "kernels": [kernel_name(q) for q in d["passes"]]}
+            stages = sum(int(math.log2(q["N"])) // 4 for q in d["passes"] if q["mfma"] != "none")
+            if stages:
+                # 6 MFMA 16x16x32 per 16 butterflies of a stage: 384 flops a point.
+                tf = 384.0 * stages * n * B / (ms * 1e-3) / 1e12
+                r["mfma_stages"] = stages
+                r["mfma_tflops"] = round(tf, 1)
+                r["mfma_frac_dense_peak"] = round(tf / MFMA_DENSE_PEAK_TFLOPS, 4)
+            bound = 2e-6 * math.log2(n) if prec != "split_bf16" else 2.0 * stages * 2.0 ** -16
+            samples["mfma_" + prec] = [(xs[i], ym.view(B, n)[rows[i]].cpu().numpy(), bound) for i in range(len(rows))]
+            rec[prec] = r
+            p.close()
+        ex["split_mfma_b256_2^20"] = rec
+        del xm, ym
 
-    # Differentiable workload: forward + adjoint, 256 x 2^16, lift <256 256>.
-    n, B = 1 << 16, 256
-    p = mfft.Plan(n, B, [256, 256])
-    xa = inputs.device_uniform_complex(n * B, args.seed + 1, torch.complex64, dev)
-    ya = torch.empty_like(xa)
-    za = torch.empty_like(xa)
+    if want("tuned"):
+        # The autotuner's lift and tile widths for n = 2^24 (up to three levels).
+        with tempfile.TemporaryDirectory() as td:
+            os.environ["MOA_FFT_TUNE_CACHE"] = os.path.join(td, "tune.json")
+            best = tune.tune(1 << 24, 1, max_levels=3, reps=5, use_cache=False)
+        ex["tuned_2^24"] = {"lift": best["lift"], "tuning": best["tuning"], "ms": round(best["ms"], 5),
+                            "gflops": round(gflops(1 << 24, 1, best["ms"] * 1e-3), 1), "candidates": best["tried"]}
 
-    def fwd_adj():
-        p.forward(xa, out=ya)
-        p.adjoint(ya, out=za)
-    fwd_adj()
-    ms = time_events(fwd_adj, reps, torch)
-    ex["fwd_adj_b256_2^16"] = {"ms": round(ms, 5), "gflops": round(2 * gflops(n, B, ms * 1e-3), 1),
-                               "hbm_gbs": round(4 * 16 * n * B / (ms * 1e-3) / 1e9, 1)}
-    p.close()
-    del xa, ya, za
-
-    # Split-precision matrix-core levels vs FP32, 256 x 2^20, lift <256 4096>.
-    n, B, lift = 1 << 20, 256, [256, 4096]
-    xm = inputs.device_uniform_complex(n * B, args.seed + 3, torch.complex64, dev)
-    ym = torch.empty_like(xm)
-    rows = [0, B - 1]
-    xs = xm.view(B, n)[rows].cpu().numpy()
-    rec = {"lift": lift}
-    for prec in ("native", "split_bf16", "split_fp16"):
-        p = mfft.Plan(n, B, lift, prec=prec)
-        d = p.describe()
-        p.forward(xm, out=ym)
-        mreps = max(3, reps // 2)
-        ms = time_events(lambda: p.forward(xm, out=ym), mreps, torch)
-        lv = level_times_in_chain(p, xm, ym, mreps, torch)
-        levels = len(d["passes"])
-        r = {"ms": round(ms, 4), "gflops": round(gflops(n, B, ms * 1e-3), 1),
-             "hbm_gbs": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9, 1),
-             "level_ms": [round(v, 4) for v in lv], "kernels": [kernel_name(q) for q in d["passes"]]}
-        stages = sum(int(math.log2(q["N"])) // 4 for q in d["passes"] if q["mfma"] != "none")
-        if stages:
-            # 6 MFMA 16x16x32 per 16 butterflies of a stage: 384 flops a point.
-            tf = 384.0 * stages * n * B / (ms * 1e-3) / 1e12
-            r["mfma_stages"] = stages
-            r["mfma_tflops"] = round(tf, 1)
-            r["mfma_frac_dense_peak"] = round(tf / MFMA_DENSE_PEAK_TFLOPS, 4)
-        bound = 2e-6 * math.log2(n) if prec != "split_bf16" else 2.0 * stages * 2.0 ** -16
-        samples["mfma_" + prec] = [(xs[i], ym.view(B, n)[rows[i]].cpu().numpy(), bound) for i in range(len(rows))]
-        rec[prec] = r
+    if want("c128"):
+        # Latency of the complex128 n = 2^10 transform (single workgroup).
+        p = mfft.Plan(1 << 10, 1, None, dtype=torch.complex128)
+        xc = inputs.device_uniform_complex(1 << 10, args.seed + 2, torch.complex128, dev)
+        yc = torch.empty_like(xc)
+        for _ in range(10):
+            p.forward(xc, out=yc)
+        ex["c128_n1024_us_per_call"] = round(1e3 * time_events(lambda: p.forward(xc, out=yc), 200, torch), 3)
+        samples["c128_n1024"] = [(xc.cpu().numpy(), yc.cpu().numpy(), 1e-13)]
         p.close()
-    ex["split_mfma_b256_2^20"] = rec
-    del xm, ym
-
-    # The autotuner's lift and tile widths for n = 2^24 (up to three levels).
-    with tempfile.TemporaryDirectory() as td:
-        os.environ["MOA_FFT_TUNE_CACHE"] = os.path.join(td, "tune.json")
-        best = tune.tune(1 << 24, 1, max_levels=3, reps=5, use_cache=False)
-    ex["tuned_2^24"] = {"lift": best["lift"], "tuning": best["tuning"], "ms": round(best["ms"], 5),
-                        "gflops": round(gflops(1 << 24, 1, best["ms"] * 1e-3), 1), "candidates": best["tried"]}
-
-    # Latency of the complex128 n = 2^10 transform (single workgroup).
-    p = mfft.Plan(1 << 10, 1, None, dtype=torch.complex128)
-    xc = inputs.device_uniform_complex(1 << 10, args.seed + 2, torch.complex128, dev)
-    yc = torch.empty_like(xc)
-    for _ in range(10):
-        p.forward(xc, out=yc)
-    ex["c128_n1024_us_per_call"] = round(1e3 * time_events(lambda: p.forward(xc, out=yc), 200, torch), 3)
-    samples["c128_n1024"] = [(xc.cpu().numpy(), yc.cpu().numpy(), 1e-13)]
-    p.close()
     return ex, samples
 
 
@@ -415,6 +425,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error statement)")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of extra workloads: uneven, fwd_adj, split_mfma, tuned, c128 (default all)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device copy of the same buffer (reference for HBM counters)")
     args = ap.parse_args()
