@@ -160,7 +160,7 @@ __device__ __forceinline__ int batch_run(const BatchArgs& a, int ti, typename cp
     if constexpr (LGN == 14 && sizeof(R) == 4) {
         for (; same(ti); ti += G) {
             asm volatile("" : "+v"(tt));
-            split14_run<FWD>(a, a.toff[a.tasks[ti].first], lds, tl, tab, tt);
+            split14_run<FWD>(a, a.tasks[ti].off0, lds, tl, tab, tt);
             __syncthreads();  // the next task overwrites the LDS exchange area
         }
         return ti;
@@ -176,7 +176,14 @@ __device__ __forceinline__ int batch_run(const BatchArgs& a, int ti, typename cp
             const BatchTask tk = a.tasks[ti];
             const int w = tt >> LGTPC;
             const bool active = w < tk.count;
-            const int64_t off = active ? a.toff[tk.first + w] : 0;
+            // A 2^13-point task holds one transform: its offset comes with the
+            // descriptor, one dependent load fewer before the data loads.
+            int64_t off = 0;
+            if constexpr (LGN == 13) {
+                off = tk.off0;
+            } else {
+                if (active) off = a.toff[tk.first + w];
+            }
             if (active) task_load<R, LGN>(v, in, off, tt);
             if constexpr (kTableWithTask<R>) store_table(tl, tab, tt);
             task_run<R, LGN>(v, out, off, active, lds, tl, R(a.sign), tt);

@@ -121,6 +121,7 @@ struct BatchTask {
     int32_t lgn;
     int32_t count;
     int64_t first;
+    int64_t off0;                 // toff[first], so a one-transform task needs no offset load
 };
 
 struct BatchArgs {

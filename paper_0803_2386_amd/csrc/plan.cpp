@@ -718,6 +718,7 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
             tk.lgn = lg;
             tk.count = cnt;
             tk.first = int64_t(p->toff.size());
+            tk.off0 = off[size_t(idx[k])];
             for (int w = 0; w < cnt; ++w) p->toff.push_back(off[size_t(idx[k + size_t(w)])]);
             p->tasks.push_back(tk);
             if (uses_lds) lds_max = std::max(lds_max, int(int64_t(cnt) * cs * int64_t(eb)));
