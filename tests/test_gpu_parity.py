@@ -115,6 +115,49 @@ def test_closed_forms_on_gpu():
         assert np.abs(got - want).max() < 2e-6 * np.log2(n) * np.sqrt(n) * 4
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_maximum_size_sparse_spectrum(dtype):
+    """n = 2^30, the largest size the library plans (default lift).  The input
+    is a sum of seeded complex exponentials generated on the device in FP64
+    (phases from the exact integer product j k mod n), so the exact transform
+    is n a_t at bin k_t (forward) or -k_t mod n (adjoint) and 0 elsewhere.
+    The whole output is compared with that by relative L2, summed in FP64 in
+    chunks on the device, to the same tolerance as the oracle comparisons."""
+    need_gpu()
+    n, C = 1 << 30, 1 << 24
+    rng = np.random.default_rng(30)
+    ks = sorted({0, 1, n // 2, n - 1, *(int(k) for k in rng.integers(0, n, 4))})
+    amps = rng.uniform(-1, 1, len(ks)) + 1j * rng.uniform(-1, 1, len(ks))
+    dev = torch.device("cuda", 0)
+    kt = torch.tensor(ks, dtype=torch.int64, device=dev)
+    at = torch.tensor(amps, dtype=torch.complex128, device=dev)
+    x = torch.empty(n, dtype=dtype, device=dev)
+    for s in range(0, n, C):
+        j = torch.arange(s, s + C, dtype=torch.int64, device=dev)
+        ph = ((j[:, None] * kt[None, :]) % n).to(torch.float64) * (2 * np.pi / n)
+        x[s:s + C] = (torch.polar(torch.ones_like(ph), ph) * at[None, :]).sum(1).to(dtype)
+        del j, ph
+    plan = mfft.Plan(n, 1, None, dtype=dtype)
+    den = n * float(np.sqrt(np.sum(np.abs(amps) ** 2)))
+    for direction, bins in (("forward", ks), ("adjoint", [(-k) % n for k in ks])):
+        y = plan.forward(x) if direction == "forward" else plan.adjoint(x)
+        # Error at the tone bins, then the energy everywhere else (the bins
+        # zeroed first: no difference of two sums of size n^2 |a|^2).
+        idx = torch.tensor(bins, device=dev)
+        yt = y[idx].to(torch.complex128).cpu().numpy()
+        num2 = float(np.sum(np.abs(yt - n * amps) ** 2))
+        y[idx] = 0
+        for s in range(0, n, C):
+            num2 += float((y[s:s + C].to(torch.complex128).abs() ** 2).sum())
+        err = np.sqrt(num2) / den
+        print(f"n=2^30 {dtype} {direction}: rel L2 {err:.3e} (lift {plan.describe()['lift']})", flush=True)
+        assert err <= tol(n, dtype), (direction, err)
+        del y
+    plan.close()
+    del x
+    torch.cuda.empty_cache()
+
+
 def test_in_place_and_determinism():
     need_gpu()
     n, batch = 1 << 16, 4
