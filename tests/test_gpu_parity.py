@@ -158,6 +158,31 @@ def test_maximum_size_sparse_spectrum(dtype):
     torch.cuda.empty_cache()
 
 
+def test_misaligned_unit_stride_buffers_are_rejected():
+    """Paired-column levels move column pairs with 16-byte accesses on their
+    unit-stride side: a buffer 8 bytes off that alignment is refused before
+    any launch (MOA_ERR_ARG), on the input of a first level and on the output
+    of a last level, and the aligned calls still match the oracle."""
+    need_gpu()
+    n = 1 << 16
+    x_np = inputs.uniform_complex(n, seed=9, dtype=np.complex64)
+    want = oracle.fft(x_np.astype(np.complex128))
+    x = to_dev(x_np, torch.complex64)
+    buf = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+    mis = buf[1:]
+    assert mis.data_ptr() % 16 == 8
+    for lift, call in (([16, 4096], lambda p: p.forward(mis)),              # level 0 reads in pairs
+                       ([4096, 16], lambda p: p.forward(x, out=mis))):      # last level writes in pairs
+        p = mfft.Plan(n, 1, lift)
+        with pytest.raises(capi.MoaError) as e:
+            call(p)
+        assert e.value.status == capi.MOA_ERR_ARG
+        y = p.forward(x)
+        torch.cuda.synchronize()
+        assert rel_err_rows(y.cpu().numpy(), want) <= tol(n, torch.complex64)
+        p.close()
+
+
 def test_in_place_and_determinism():
     need_gpu()
     n, batch = 1 << 16, 4
