@@ -96,7 +96,13 @@ typedef struct {
                                    launch (0 = one per task; fewer make it
                                    persistent, each workgroup walking the
                                    tasks with a grid stride)               */
-    int32_t reserved[7];
+    int32_t stream_input;       /* loads of the caller's input (read once:
+                                   the first level, every task of an uneven
+                                   batch) as non-temporal streaming loads:
+                                   0 = when the input is at most 256 MiB
+                                   (the Infinity Cache), 1 = always,
+                                   -1 = never; other values MOA_ERR_TUNING  */
+    int32_t reserved[6];
 } moa_fft_tuning_t;
 
 /*

@@ -32,7 +32,8 @@ constexpr int kTaskPts = 16;  // register slots per thread
 
 // Loads of this thread's points of a task of 2^LGN-point transforms (slot
 // order of stage 0); `off` is the element offset of the thread's transform.
-template <typename R, int LGN, typename V>
+// ONCE: streaming loads (a batch reads each input element once).
+template <typename R, int LGN, bool ONCE, typename V>
 __device__ __forceinline__ void task_load(V (&v)[kTaskPts], const V* __restrict__ in, int64_t off, int t)
 {
     constexpr int LGE = task_lge<R, LGN>();
@@ -41,7 +42,7 @@ __device__ __forceinline__ void task_load(V (&v)[kTaskPts], const V* __restrict_
     const int j = t & (TPC - 1);
     const V* src = in + off + j;
 #pragma unroll
-    for (int m = 0; m < (1 << LE); ++m) v[in_slot<LGN, LGE>(m)] = src[m * TPC];
+    for (int m = 0; m < (1 << LE); ++m) v[in_slot<LGN, LGE>(m)] = ONCE ? load_once(src + m * TPC) : src[m * TPC];
 }
 
 // Stages and store of one task (loads already in v).
@@ -116,12 +117,16 @@ __device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, flo
     const V* __restrict__ src = reinterpret_cast<const V*>(a.in) + off;
     V* __restrict__ dst = reinterpret_cast<V*>(a.out) + off;
     V e[E], o[E];
+    auto ld = [&](auto once) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int i = 2 * (t + m * TPC);
-        e[in_slot<LGH, 4>(m)] = src[i];
-        o[in_slot<LGH, 4>(m)] = src[i + 1];
-    }
+        for (int m = 0; m < E; ++m) {
+            const int i = 2 * (t + m * TPC);
+            e[in_slot<LGH, 4>(m)] = once ? load_once(src + i) : src[i];
+            o[in_slot<LGH, 4>(m)] = once ? load_once(src + i + 1) : src[i + 1];
+        }
+    };
+    if (a.nt_in) ld(std::true_type{});
+    else ld(std::false_type{});
     store_table(tl, tab, t);
     pair_stages<FWD, LGH, 0>(e, o, lds, t, tl);
     // w^k for k = t + rank * TPC: base w^t times the powers w^(TPC 2^b) of
@@ -184,7 +189,10 @@ __device__ __forceinline__ int batch_run(const BatchArgs& a, int ti, typename cp
             } else {
                 if (active) off = a.toff[tk.first + w];
             }
-            if (active) task_load<R, LGN>(v, in, off, tt);
+            if (active) {
+                if (a.nt_in) task_load<R, LGN, true>(v, in, off, tt);
+                else task_load<R, LGN, false>(v, in, off, tt);
+            }
             if constexpr (kTableWithTask<R>) store_table(tl, tab, tt);
             task_run<R, LGN>(v, out, off, active, lds, tl, R(a.sign), tt);
             __syncthreads();  // the next task overwrites the LDS exchange area

@@ -271,6 +271,30 @@ __device__ __forceinline__ V tw_inter32(const V* tt, int parts, uint32_t e)
     return w;
 }
 
+// Loads of the caller's input, which a transform reads exactly once (its
+// first level; every task of an uneven batch): non-temporal (streaming)
+// loads leave the caches to the data that is read again -- the workspace a
+// level has just written and the next level reads.  On the 2^24-point
+// transform the first level runs in 79 us with them against 108 us without.
+__device__ __forceinline__ float2 load_once(const float2* p)
+{
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 x = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return make_float2(x.x, x.y);
+}
+__device__ __forceinline__ double2 load_once(const double2* p)
+{
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 x = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return make_double2(x.x, x.y);
+}
+__device__ __forceinline__ float4 load_once(const float4* p)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 x = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    return make_float4(x.x, x.y, x.z, x.w);
+}
+
 template <int LGN, int LGE, int S>
 struct StageTw {
     static constexpr int N = 1 << LGN;

@@ -108,6 +108,7 @@ struct PassArgs {
     int xcd_remap;
     int pre_lg;                   // log2 of the points transformed by earlier levels
     float sign;                   // -1 forward, +1 adjoint
+    int nt_in;                    // 1: `in` is the caller's input, read once (streaming loads)
     // Blocked layouts (see PassDesc); the tile strides are always set.
     int in_lgb, out_lgb;
     int64_t in_s_hi, out_s_hi;
@@ -134,6 +135,7 @@ struct BatchArgs {
     int task0;                    // first task of this launch
     int data_elems;               // LDS elements of the exchange tile (the twiddle table follows)
     float sign;
+    int nt_in;                    // 1: streaming loads of `in`
 };
 
 // Launchers (fft_kernels.hip / fft_batched.hip / fft_mfma.hip).  They return

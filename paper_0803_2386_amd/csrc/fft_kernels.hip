@@ -38,8 +38,15 @@ __device__ __forceinline__ void prefetch_now(const PassArgs& a, uint64_t tile_id
     constexpr int TPC = 1 << (LGN - LE);
     tile_offsets(a, tile_id, d0, ib, ob);
     const V* src = gin + ib + int64_t(w) * a.in_s[0];
+    // The caller's input streams past the caches (complex64; the complex128
+    // kernels keep one load path, their registers are full).
+    if (sizeof(V) == 8 && a.nt_in) {
 #pragma unroll
-    for (int m = 0; m < (1 << LE); ++m) vn[in_slot<LGN, LGE>(m)] = src[int64_t(j + m * TPC) * a.in_s_e];
+        for (int m = 0; m < (1 << LE); ++m) vn[in_slot<LGN, LGE>(m)] = load_once(src + int64_t(j + m * TPC) * a.in_s_e);
+    } else {
+#pragma unroll
+        for (int m = 0; m < (1 << LE); ++m) vn[in_slot<LGN, LGE>(m)] = src[int64_t(j + m * TPC) * a.in_s_e];
+    }
 }
 
 // Kernel modes: 0 = 16 points a thread, <= 512 threads, next tile prefetched;
@@ -105,8 +112,13 @@ __global__ void __launch_bounds__(mode_threads(KM)) k_pass(PassArgs a)
     if (tile < end) {
         tile_offsets(a, tile, d0, ib, ob);
         const V* src = gin + ib + int64_t(w) * a.in_s[0];
+        if (sizeof(V) == 8 && a.nt_in) {  // as in prefetch_now
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[in_slot<LGN, LGE>(m)] = src[int64_t(j + m * TPC) * a.in_s_e];
+            for (int m = 0; m < E; ++m) v[in_slot<LGN, LGE>(m)] = load_once(src + int64_t(j + m * TPC) * a.in_s_e);
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[in_slot<LGN, LGE>(m)] = src[int64_t(j + m * TPC) * a.in_s_e];
+        }
     }
     // Mode 2 runs one tile per workgroup (grid = tiles): without a prefetch a
     // tile loop buys nothing and costs registers.

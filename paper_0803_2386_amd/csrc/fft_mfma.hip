@@ -135,7 +135,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
                     w = i >> LGN;
                 }
                 slot[m] = w * cs + lds_pad(e);
-                tmp[m] = src[int64_t(w) * a.in_s[0] + int64_t(e) * a.in_s_e];
+                const V* p = src + int64_t(w) * a.in_s[0] + int64_t(e) * a.in_s_e;
+                tmp[m] = a.nt_in ? load_once(p) : *p;
             }
 #pragma unroll
             for (int m = 0; m < 16; ++m) lds[slot[m]] = tmp[m];
@@ -433,21 +434,34 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
     {
         const uint32_t se = uint32_t(a.in_s_e) * 8u, s0 = uint32_t(a.in_s[0]) * 8u;
         const uint32_t step = uint32_t(TPC) * se;
+        // The caller's input (first level) streams past the caches.
+        const bool once = a.nt_in != 0;
         if constexpr (TIN) {
             const uint32_t off = 16u * uint32_t(ui) + uint32_t(ji) * se;
+            auto ld = [&](bool nt) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const float4 x = *reinterpret_cast<const float4*>(mat(gin, off + uint32_t(m) * step));
-                v0[m] = make_float2(x.x, x.y);
-                v1[m] = make_float2(x.z, x.w);
-            }
+                for (int m = 0; m < E; ++m) {
+                    const float4* p = reinterpret_cast<const float4*>(mat(gin, off + uint32_t(m) * step));
+                    const float4 x = nt ? load_once(p) : *p;
+                    v0[m] = make_float2(x.x, x.y);
+                    v1[m] = make_float2(x.z, x.w);
+                }
+            };
+            if (once) ld(true);
+            else ld(false);
         } else {
             const uint32_t o0 = 2u * uint32_t(ui) * s0 + uint32_t(ji) * se, o1 = o0 + s0;
+            auto ld = [&](bool nt) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                v0[m] = *mat(gin, o0 + uint32_t(m) * step);
-                v1[m] = *mat(gin, o1 + uint32_t(m) * step);
-            }
+                for (int m = 0; m < E; ++m) {
+                    const V* p0 = mat(gin, o0 + uint32_t(m) * step);
+                    const V* p1 = mat(gin, o1 + uint32_t(m) * step);
+                    v0[m] = nt ? load_once(p0) : *p0;
+                    v1[m] = nt ? load_once(p1) : *p1;
+                }
+            };
+            if (once) ld(true);
+            else ld(false);
         }
     }
 #pragma unroll

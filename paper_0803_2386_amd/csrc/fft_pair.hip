@@ -85,20 +85,33 @@ __device__ __forceinline__ void pair_tile(const PassArgs& a, uint64_t tile)
         const uint32_t s0 = uint32_t(a.in_s[0]) * 8u;
         const uint32_t step = row(uint32_t(TPC), a.in_lgb, se, shi) * 8u;
         const uint32_t o0 = (uu * uint32_t(a.in_pair_s) + row(ju, a.in_lgb, se, shi)) * 8u;
+        // The caller's input (first level) streams past the caches.
+        const bool once = a.nt_in != 0;
         if constexpr (TIN) {
+            auto ld = [&](bool nt) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const float4 x = *reinterpret_cast<const float4*>(at(gin, o0 + uint32_t(m) * step));
-                v0[in_slot<LGN, 4>(m)] = make_float2(x.x, x.y);
-                v1[in_slot<LGN, 4>(m)] = make_float2(x.z, x.w);
-            }
+                for (int m = 0; m < E; ++m) {
+                    const float4* p = reinterpret_cast<const float4*>(at(gin, o0 + uint32_t(m) * step));
+                    const float4 x = nt ? load_once(p) : *p;
+                    v0[in_slot<LGN, 4>(m)] = make_float2(x.x, x.y);
+                    v1[in_slot<LGN, 4>(m)] = make_float2(x.z, x.w);
+                }
+            };
+            if (once) ld(true);
+            else ld(false);
         } else {
             const uint32_t o1 = o0 + s0;
+            auto ld = [&](bool nt) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                v0[in_slot<LGN, 4>(m)] = *at(gin, o0 + uint32_t(m) * step);
-                v1[in_slot<LGN, 4>(m)] = *at(gin, o1 + uint32_t(m) * step);
-            }
+                for (int m = 0; m < E; ++m) {
+                    const V* p0 = at(gin, o0 + uint32_t(m) * step);
+                    const V* p1 = at(gin, o1 + uint32_t(m) * step);
+                    v0[in_slot<LGN, 4>(m)] = nt ? load_once(p0) : *p0;
+                    v1[in_slot<LGN, 4>(m)] = nt ? load_once(p1) : *p1;
+                }
+            };
+            if (once) ld(true);
+            else ld(false);
         }
     }
 #pragma unroll

@@ -183,6 +183,36 @@ def test_misaligned_unit_stride_buffers_are_rejected():
         p.close()
 
 
+def test_streaming_and_plain_input_loads_agree_bitwise():
+    """The first level's loads of the caller's input run as streaming or as
+    plain loads (tuning stream_input 1 / -1): same arithmetic, so the outputs
+    are equal bit for bit, on the paired-column, the persistent and the
+    uneven-batch kernels, and match the oracle."""
+    need_gpu()
+    for n, batch, lift in ((1 << 16, 1, [16, 4096]), (1 << 16, 2, [256, 256]), (1 << 12, 3, None)):
+        x_np = inputs.uniform_complex((batch, n), seed=11, dtype=np.complex64)
+        x = to_dev(x_np, torch.complex64)
+        outs = []
+        for mode in (1, -1):
+            p = mfft.Plan(n, batch, lift, tuning={"stream_input": mode})
+            assert p.describe()["stream_input"] == (mode == 1)
+            outs.append(p.forward(x))
+            p.close()
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], outs[1])
+        want = oracle.fft(x_np.astype(np.complex128))
+        assert rel_err_rows(outs[0].cpu().numpy(), want) <= tol(n, torch.complex64)
+    sizes = [64, 16384, 1, 8192, 128, 4096]
+    xb = to_dev(inputs.uniform_complex(sum(sizes), seed=12, dtype=np.complex64), torch.complex64)
+    outs = []
+    for mode in (1, -1):
+        p = mfft.BatchedPlan(sizes, tuning={"stream_input": mode})
+        outs.append(p.forward(xb))
+        p.close()
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+
+
 def test_in_place_and_determinism():
     need_gpu()
     n, batch = 1 << 16, 4
