@@ -96,9 +96,10 @@ typedef struct {
                                    launch (0 = one per task; fewer make it
                                    persistent, each workgroup walking the
                                    tasks with a grid stride)               */
-    int32_t stream_input;       /* loads of the caller's input (read once:
-                                   the first level, every task of an uneven
-                                   batch) as non-temporal streaming loads:
+    int32_t stream;             /* non-temporal (streaming) access to data a
+                                   transform touches once: the first level's
+                                   loads of the caller's input; for an
+                                   uneven batch its loads and its stores.
                                    0 = when the input is at most 256 MiB
                                    (the Infinity Cache), 1 = always,
                                    -1 = never; other values MOA_ERR_TUNING  */

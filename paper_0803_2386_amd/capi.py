@@ -47,7 +47,7 @@ EXPORTED = [
 class moa_fft_tuning_t(ctypes.Structure):
     _fields_ = [("cols_per_block", ctypes.c_int32 * 8),
                 ("persistent_blocks", ctypes.c_int32),
-                ("stream_input", ctypes.c_int32),
+                ("stream", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 6)]
 
 
@@ -116,7 +116,7 @@ def _tuning(tuning):
     for i, v in enumerate(tuning.get("cols_per_block", [])[:8]):
         t.cols_per_block[i] = int(v)
     t.persistent_blocks = int(tuning.get("persistent_blocks", 0))
-    t.stream_input = int(tuning.get("stream_input", 0))
+    t.stream = int(tuning.get("stream", 0))
     return ctypes.pointer(t)
 
 

@@ -45,25 +45,34 @@ __device__ __forceinline__ void task_load(V (&v)[kTaskPts], const V* __restrict_
     for (int m = 0; m < (1 << LE); ++m) v[in_slot<LGN, LGE>(m)] = ONCE ? load_once(src + m * TPC) : src[m * TPC];
 }
 
-// Stages and store of one task (loads already in v).
+// Stages of one task (loads already in v).
 template <typename R, int LGN>
-__device__ __forceinline__ void task_run(typename cpx<R>::V (&v)[kTaskPts], typename cpx<R>::V* __restrict__ out,
-                                         int64_t off, bool active, typename cpx<R>::V* lds,
-                                         const typename cpx<R>::V* tl, R sign, int t)
+__device__ __forceinline__ void task_stages(typename cpx<R>::V (&v)[kTaskPts], bool active,
+                                            typename cpx<R>::V* lds, const typename cpx<R>::V* tl, R sign, int t)
 {
     using V = typename cpx<R>::V;
     constexpr int LGE = task_lge<R, LGN>();
-    constexpr int LE = lg_e(LGN, LGE);
-    constexpr int LGTPC = LGN - LE;
+    constexpr int LGTPC = LGN - lg_e(LGN, LGE);
     constexpr int TPC = 1 << LGTPC;
     constexpr int CS = lds_col_stride(1 << LGN, TPC);
     const int j = t & (TPC - 1), w = t >> LGTPC;
     V tw[kMaxStageTw];
     run_stages<R, LGN, LGE, 0, false>(v, lds + w * CS, j, sign, tl, active, tw);
-    if (active) {
-        V* dst = out + off + j;
+}
+
+// Stores of one task (ONCE: streaming stores).
+template <typename R, int LGN, bool ONCE, typename V>
+__device__ __forceinline__ void task_store(const V (&v)[kTaskPts], V* __restrict__ out, int64_t off, int t)
+{
+    constexpr int LGE = task_lge<R, LGN>();
+    constexpr int LE = lg_e(LGN, LGE);
+    constexpr int TPC = 1 << (LGN - LE);
+    V* dst = out + off + (t & (TPC - 1));
 #pragma unroll
-        for (int m = 0; m < (1 << LE); ++m) dst[out_slot_rank<LGN, LGE>(m) * TPC] = v[m];
+    for (int m = 0; m < (1 << LE); ++m) {
+        V* q = dst + out_slot_rank<LGN, LGE>(m) * TPC;
+        if (ONCE) store_once(q, v[m]);
+        else *q = v[m];
     }
 }
 
@@ -125,7 +134,7 @@ __device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, flo
             o[in_slot<LGH, 4>(m)] = once ? load_once(src + i + 1) : src[i + 1];
         }
     };
-    if (a.nt_in) ld(std::true_type{});
+    if (a.nt) ld(std::true_type{});
     else ld(std::false_type{});
     store_table(tl, tab, t);
     pair_stages<FWD, LGH, 0>(e, o, lds, t, tl);
@@ -136,13 +145,23 @@ __device__ __forceinline__ void split14_run(const BatchArgs& a, int64_t off, flo
 #pragma unroll
     for (int b = 0; b < 4; ++b) pw[b] = tw_blk(tl, TPC << b);
     power_tree<4, false>(f, pw);
+    auto st = [&](auto once) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int rank = out_slot_rank<LGH, 4>(m);
-        const V p = cmul_dir<FWD>(o[m], f[rank]);
-        dst[t + rank * TPC] = cadd(e[m], p);
-        dst[t + rank * TPC + (1 << LGH)] = csub(e[m], p);
-    }
+        for (int m = 0; m < E; ++m) {
+            const int rank = out_slot_rank<LGH, 4>(m);
+            const V p = cmul_dir<FWD>(o[m], f[rank]);
+            V* q = dst + t + rank * TPC;
+            if (once) {
+                store_once(q, cadd(e[m], p));
+                store_once(q + (1 << LGH), csub(e[m], p));
+            } else {
+                q[0] = cadd(e[m], p);
+                q[1 << LGH] = csub(e[m], p);
+            }
+        }
+    };
+    if (a.nt) st(std::true_type{});
+    else st(std::false_type{});
 }
 
 // The run of this workgroup's tasks (ti, ti + G, ...) that hold transforms
@@ -190,11 +209,15 @@ __device__ __forceinline__ int batch_run(const BatchArgs& a, int ti, typename cp
                 if (active) off = a.toff[tk.first + w];
             }
             if (active) {
-                if (a.nt_in) task_load<R, LGN, true>(v, in, off, tt);
+                if (a.nt) task_load<R, LGN, true>(v, in, off, tt);
                 else task_load<R, LGN, false>(v, in, off, tt);
             }
             if constexpr (kTableWithTask<R>) store_table(tl, tab, tt);
-            task_run<R, LGN>(v, out, off, active, lds, tl, R(a.sign), tt);
+            task_stages<R, LGN>(v, active, lds, tl, R(a.sign), tt);
+            if (active) {
+                if (a.nt) task_store<R, LGN, true>(v, out, off, tt);
+                else task_store<R, LGN, false>(v, out, off, tt);
+            }
             __syncthreads();  // the next task overwrites the LDS exchange area
         }
         return ti;

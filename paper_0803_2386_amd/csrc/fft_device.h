@@ -295,6 +295,19 @@ __device__ __forceinline__ float4 load_once(const float4* p)
     return make_float4(x.x, x.y, x.z, x.w);
 }
 
+// Stores of output a transform writes once and does not read back (an
+// uneven batch's full-line stores): non-temporal.
+__device__ __forceinline__ void store_once(float2* p, float2 v)
+{
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store((v2){v.x, v.y}, reinterpret_cast<v2*>(p));
+}
+__device__ __forceinline__ void store_once(double2* p, double2 v)
+{
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store((v2){v.x, v.y}, reinterpret_cast<v2*>(p));
+}
+
 template <int LGN, int LGE, int S>
 struct StageTw {
     static constexpr int N = 1 << LGN;

@@ -135,7 +135,7 @@ struct BatchArgs {
     int task0;                    // first task of this launch
     int data_elems;               // LDS elements of the exchange tile (the twiddle table follows)
     float sign;
-    int nt_in;                    // 1: streaming loads of `in`
+    int nt;                       // 1: streaming loads of `in` and stores of `out`
 };
 
 // Launchers (fft_kernels.hip / fft_batched.hip / fft_mfma.hip).  They return

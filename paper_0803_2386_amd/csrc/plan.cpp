@@ -96,7 +96,7 @@ struct moa_fft_plan_s {
     void* d_toff = nullptr;
     int device = -1;
     int cus = 256;                 // compute units of the device (for persistent grids)
-    bool stream_in = false;        // streaming loads of the caller's input
+    bool stream = false;           // streaming access to data touched once (see moa_fft_tuning_t)
     std::vector<GraphEntry> graphs;
     std::mutex mu;
 };
@@ -484,8 +484,8 @@ std::string describe_json(const moa_fft_plan_s* p)
         p->batched ? "uneven_batch" : "lifted", p->fp64 ? "c128" : "c64",
         p->prec == MOA_FFT_PREC_NATIVE ? "native" : (p->prec == MOA_FFT_PREC_SPLIT_BF16 ? "split_bf16" : "split_fp16"),
         (long long)p->n, (long long)p->batch, (long long)p->total);
-    add("\"host_only\":%s,\"workspace_bytes\":%zu,\"stream_input\":%s,", p->host_only ? "true" : "false",
-        p->ws_bytes, p->stream_in ? "true" : "false");
+    add("\"host_only\":%s,\"workspace_bytes\":%zu,\"stream\":%s,", p->host_only ? "true" : "false",
+        p->ws_bytes, p->stream ? "true" : "false");
     s += "\"lift\":[";
     for (size_t i = 0; i < p->lift.size(); ++i) add("%s%lld", i ? "," : "", (long long)p->lift[i]);
     s += "],\"levels\":[";
@@ -537,17 +537,20 @@ moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, G
 moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, hipStream_t s);
 
 // Fill the kernel argument blocks of every pass for one execution.
-// Streaming (non-temporal) loads of the caller's input, which a transform
-// reads once.  While the input fits the 256 MiB Infinity Cache they keep it
-// from displacing the workspace the next level reads (measured: the first
-// level of the 2^24-point transform 108 -> 79 us, the 8192-transform uneven
-// batch 100 -> 90 us); a 2 GiB input gains nothing and ran a few per cent
-// slower with them, so the automatic choice is by size.
+// Streaming (non-temporal) access to data a transform touches once: the
+// first level's loads of the caller's input (while it fits the 256 MiB
+// Infinity Cache they keep it from displacing the workspace the next level
+// reads: the first level of the 2^24-point transform 108 -> 79 us; a 2 GiB
+// input ran a few per cent slower with them, so the automatic choice is by
+// size), and for an uneven batch its loads and its full-line output stores
+// (8192 transforms: 99 -> 91 us).  Later levels read the workspace with
+// plain loads, and the partial-line stores of a lifted level stay plain;
+// streaming either was slower.
 constexpr size_t kStreamAutoBytes = size_t(256) << 20;
 
 moa_status_t stream_choice(const moa_fft_tuning_t* tuning, size_t in_bytes, bool& on)
 {
-    const int mode = tuning ? tuning->stream_input : 0;
+    const int mode = tuning ? tuning->stream : 0;
     if (mode < -1 || mode > 1) return MOA_ERR_TUNING;
     on = mode == 1 || (mode == 0 && in_bytes <= kStreamAutoBytes);
     return MOA_OK;
@@ -585,7 +588,7 @@ void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, std:
         a.xcd_remap = d.xcd_remap;
         a.pre_lg = d.pre_lg;
         a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
-        a.nt_in = (l == 0 && p->stream_in) ? 1 : 0;
+        a.nt_in = (l == 0 && p->stream) ? 1 : 0;
         a.in_lgb = d.in_lgb;
         a.out_lgb = d.out_lgb;
         a.in_s_hi = d.in_s_hi;
@@ -611,7 +614,7 @@ moa::BatchArgs batch_args(const moa_fft_plan_s* p, int dir, const void* in, void
     a.ntasks = ntasks;
     a.data_elems = p->batch_data_elems;
     a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
-    a.nt_in = p->stream_in ? 1 : 0;
+    a.nt = p->stream ? 1 : 0;
     return a;
 }
 
@@ -850,7 +853,7 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
             p->cus = cus;
     }
     st = lower(p, tuning);
-    if (st == MOA_OK) st = stream_choice(tuning, size_t(p->total) * elem_bytes(fp64), p->stream_in);
+    if (st == MOA_OK) st = stream_choice(tuning, size_t(p->total) * elem_bytes(fp64), p->stream);
     if (st != MOA_OK) {
         delete p;
         return st;
@@ -882,7 +885,7 @@ moa_status_t moa_fft_plan_batched_tuned(moa_fft_plan_t* out, const int64_t* size
     p->sizes.assign(sizes, sizes + count);
     p->batch = count;
     st = plan_uneven(p, tuning);
-    if (st == MOA_OK) st = stream_choice(tuning, size_t(p->total) * elem_bytes(p->fp64), p->stream_in);
+    if (st == MOA_OK) st = stream_choice(tuning, size_t(p->total) * elem_bytes(p->fp64), p->stream);
     if (st != MOA_OK) {
         delete p;
         return st;

@@ -306,27 +306,27 @@ def test_batched_grid_defaults_to_one_workgroup_per_task():
                      tuning={"persistent_blocks": -1}) == capi.MOA_ERR_TUNING
 
 
-def test_stream_input_choice():
+def test_stream_choice():
     """Streaming loads of the caller's input: automatic while the input is at
     most 256 MiB, forced on or off by the tuning field, other values refused."""
     def stream(n, dtype=capi.MOA_C64, tuning=None):
         h = capi.moa_fft_plan(n, 1, None, dtype, capi.MOA_FFT_PREC_NATIVE, HOST, tuning)
         try:
-            return json.loads(capi.moa_fft_describe(h))["stream_input"]
+            return json.loads(capi.moa_fft_describe(h))["stream"]
         finally:
             capi.moa_fft_destroy(h)
 
     assert stream(1 << 24) and stream(1 << 25)              # 128 and 256 MiB
     assert not stream(1 << 26)                              # 512 MiB
     assert not stream(1 << 25, capi.MOA_C128)               # 512 MiB
-    assert stream(1 << 28, tuning={"stream_input": 1})
-    assert not stream(1 << 10, tuning={"stream_input": -1})
+    assert stream(1 << 28, tuning={"stream": 1})
+    assert not stream(1 << 10, tuning={"stream": -1})
     for bad in (2, -2):
         assert status_of(capi.moa_fft_plan, 1 << 10, 1, None, capi.MOA_C64, capi.MOA_FFT_PREC_NATIVE, HOST,
-                         {"stream_input": bad}) == capi.MOA_ERR_TUNING
+                         {"stream": bad}) == capi.MOA_ERR_TUNING
     h = capi.moa_fft_plan_batched([64, 16384] * 10, flags=HOST)
     try:
-        assert json.loads(capi.moa_fft_describe(h))["stream_input"]
+        assert json.loads(capi.moa_fft_describe(h))["stream"]
     finally:
         capi.moa_fft_destroy(h)
 

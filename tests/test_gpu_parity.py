@@ -185,7 +185,7 @@ def test_misaligned_unit_stride_buffers_are_rejected():
 
 def test_streaming_and_plain_input_loads_agree_bitwise():
     """The first level's loads of the caller's input run as streaming or as
-    plain loads (tuning stream_input 1 / -1): same arithmetic, so the outputs
+    plain loads (tuning stream 1 / -1): same arithmetic, so the outputs
     are equal bit for bit, on the paired-column, the persistent and the
     uneven-batch kernels, and match the oracle."""
     need_gpu()
@@ -194,8 +194,8 @@ def test_streaming_and_plain_input_loads_agree_bitwise():
         x = to_dev(x_np, torch.complex64)
         outs = []
         for mode in (1, -1):
-            p = mfft.Plan(n, batch, lift, tuning={"stream_input": mode})
-            assert p.describe()["stream_input"] == (mode == 1)
+            p = mfft.Plan(n, batch, lift, tuning={"stream": mode})
+            assert p.describe()["stream"] == (mode == 1)
             outs.append(p.forward(x))
             p.close()
         torch.cuda.synchronize()
@@ -206,7 +206,7 @@ def test_streaming_and_plain_input_loads_agree_bitwise():
     xb = to_dev(inputs.uniform_complex(sum(sizes), seed=12, dtype=np.complex64), torch.complex64)
     outs = []
     for mode in (1, -1):
-        p = mfft.BatchedPlan(sizes, tuning={"stream_input": mode})
+        p = mfft.BatchedPlan(sizes, tuning={"stream": mode})
         outs.append(p.forward(xb))
         p.close()
     torch.cuda.synchronize()
