@@ -109,6 +109,7 @@ struct PassArgs {
     int pre_lg;                   // log2 of the points transformed by earlier levels
     float sign;                   // -1 forward, +1 adjoint
     int nt_in;                    // 1: `in` is the caller's input, read once (streaming loads)
+    int nt_out;                   // 1: streaming stores of full-line output runs (complex64 k_pass)
     // Blocked layouts (see PassDesc); the tile strides are always set.
     int in_lgb, out_lgb;
     int64_t in_s_hi, out_s_hi;

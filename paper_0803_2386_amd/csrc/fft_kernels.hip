@@ -194,8 +194,13 @@ __global__ void __launch_bounds__(mode_threads(KM)) k_pass(PassArgs a)
             }
         }
         V* dst = gout + ob + int64_t(wst) * a.out_s[0];
+        if (sizeof(V) == 8 && a.nt_out) {  // output written once, in whole lines
 #pragma unroll
-        for (int m = 0; m < E; ++m) dst[int64_t(jst + rank(m) * TPC) * a.out_s_k] = v[m];
+            for (int m = 0; m < E; ++m) store_once(dst + int64_t(jst + rank(m) * TPC) * a.out_s_k, v[m]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) dst[int64_t(jst + rank(m) * TPC) * a.out_s_k] = v[m];
+        }
 
         if constexpr (!kPersistent) break;
         __syncthreads();  // the next tile overwrites the LDS exchange buffer

@@ -589,6 +589,13 @@ void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, std:
         a.pre_lg = d.pre_lg;
         a.sign = dir == MOA_FFT_FORWARD ? -1.0f : 1.0f;
         a.nt_in = (l == 0 && p->stream) ? 1 : 0;
+        // The last level's output is written once; where its runs are whole
+        // 128-byte lines (not the 64-byte runs of a paired level) the
+        // persistent kernel stores it streaming too.
+        a.nt_out = (l + 1 == P && p->stream && d.kmode != 3 && !d.mfma && !p->fp64 && d.out_tile_fast &&
+                    (int64_t(1) << d.lgw) * int64_t(eb) >= 128)
+                       ? 1
+                       : 0;
         a.in_lgb = d.in_lgb;
         a.out_lgb = d.out_lgb;
         a.in_s_hi = d.in_s_hi;
