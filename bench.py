@@ -260,8 +260,8 @@ def extras(args, torch, np, mfft, inputs):
 
     if want("uneven"):
         # Uneven batch: one fused launch (default grid: one workgroup per task;
-        # resident grid: persistent, two workgroups per CU) vs one plain launch
-        # per size, and the fused launch replayed from a HIP graph.
+        # resident grid: persistent, two workgroups per CU; the autotuner's
+        # grid, also replayed from a HIP graph) vs one plain launch per size.
         sizes = [int(s) for s in inputs.uneven_sizes(8192, 6, 14, seed=args.seed)]
         total = sum(sizes)
         offs = np.concatenate([[0], np.cumsum(sizes)])
@@ -282,20 +282,23 @@ def extras(args, torch, np, mfft, inputs):
                     "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
                     "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1),
                     "frac_hbm_peak": round(16 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        best = tune.tune_batched(sizes, grids=(0, resident // 2, resident, 2 * resident, 3 * resident,
+                                               4 * resident))
+        tuned = best["tuning"] or {}
         for name, kw in (("one_launch", {}), ("resident_grid", {"tuning": {"persistent_blocks": resident}}),
-                         ("per_size", {"per_size": True}), ("graph", {"graph": True})):
+                         ("per_size", {"per_size": True}), ("tuned", {"tuning": tuned}),
+                         ("tuned_graph", {"tuning": tuned, "graph": True})):
             p = mfft.BatchedPlan(sizes, **kw)
             for _ in range(3):
                 p.forward(xb, out=ob)
             ms = time_events(lambda: p.forward(xb, out=ob), reps, torch)
             rec[name] = entry(ms, p)
-            if name == "graph":
+            if name == "tuned_graph":
                 xs, ys = xb.cpu().numpy(), ob.cpu().numpy()
                 samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
                                            for i in pick]
             p.close()
-        best = tune.tune_batched(sizes, grids=(0, resident // 2, resident, 2 * resident))
-        rec["tuned"] = {"ms": round(best["ms"], 5), "grid": best["grid"]}
+        rec["tuned"]["tuner_ms"] = round(best["ms"], 5)
         # one plain launch per transform (8192 launches, timed once)
         plans = {n: mfft.Plan(n, 1, None) for n in set(sizes)}
         views = [xb[offs[i]:offs[i + 1]] for i in range(len(sizes))]
@@ -311,6 +314,7 @@ def extras(args, torch, np, mfft, inputs):
         for q in plans.values():
             q.close()
         rec["one_launch_vs_per_size"] = round(rec["per_size"]["ms"] / rec["one_launch"]["ms"], 3)
+        rec["tuned_graph_vs_per_size"] = round(rec["per_size"]["ms"] / rec["tuned_graph"]["ms"], 3)
         rec["one_launch_vs_single_launches"] = round(rec["single_launches"]["ms"] / rec["one_launch"]["ms"], 1)
         ex["uneven_batch_8192_2^6..2^14"] = rec
         del xb, ob

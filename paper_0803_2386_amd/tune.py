@@ -173,7 +173,7 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
     return best
 
 
-def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 128, 256, 384, 512, 768, 1024),
+def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 256, 512, 768, 1024, 1536, 2048),
                  reps: int = 10, verbose: bool = False) -> dict:
     """Time grids of an uneven batch's fused launch (0 = one workgroup per
     task, the default; smaller grids make it persistent); returns the best
