@@ -398,8 +398,41 @@ def extras(args, torch, np, mfft, inputs):
             p.forward(xc, out=yc)
         ex["c128_n1024_us_per_call"] = round(1e3 * time_events(lambda: p.forward(xc, out=yc), 200, torch), 3)
         samples["c128_n1024"] = [(xc.cpu().numpy(), yc.cpu().numpy(), 1e-13)]
+        ex["c128_n1024_replay"] = c128_replay_us(p, xc, torch, np)
         p.close()
     return ex, samples
+
+
+def c128_replay_us(p, x, torch, np, calls=100, replays=20):
+    """Per-call time of the single-workgroup transform without host launch
+    cost: `calls` back-to-back transforms recorded into one HIP graph (torch
+    capture of the library's launches on the capture stream), replayed
+    `replays` times, each replay timed with HIP events.  Returns the median,
+    p10 and p90 in microseconds per call, or the error text if the capture
+    fails (the eager figure stands regardless)."""
+    try:
+        out = torch.empty_like(x)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(calls):
+                p.forward(x, out=out)
+        g.replay()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(replays):
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            s.record()
+            g.replay()
+            e.record()
+            e.synchronize()
+            ms.append(s.elapsed_time(e))
+        del g
+        us = 1e3 * np.asarray(ms) / calls
+        return {"calls_per_replay": calls, "replays": replays, "median_us": round(float(np.median(us)), 3),
+                "p10_us": round(float(np.percentile(us, 10)), 3), "p90_us": round(float(np.percentile(us, 90)), 3)}
+    except Exception as exc:  # noqa: BLE001 -- reported, not fatal
+        return {"error": f"{type(exc).__name__}: {exc}"}
 
 
 def cpu_baseline_leg(args, np, result, sample, samples):

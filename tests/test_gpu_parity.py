@@ -265,3 +265,37 @@ def test_graph_replays_match_eager():
         assert torch.equal(out, ref)
         _ = eager.adjoint(ref)  # unrelated eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,batch,lift,dtype", [(1 << 10, 1, None, torch.complex128),
+                                                (1 << 16, 2, [256, 256], torch.complex64)])
+def test_launches_recorded_in_a_caller_graph(n, batch, lift, dtype):
+    """The caller may record exec into its own HIP graph (torch capture on the
+    capture stream): several back-to-back transforms, replayed with eager work
+    and synchronisations between the replays, match the eager result bit for
+    bit on every replay, and the eager result matches the oracle."""
+    need_gpu()
+    x_np = inputs.uniform_complex((batch, n), seed=11, dtype=np.complex64 if dtype == torch.complex64
+                                  else np.complex128)
+    plan = mfft.Plan(n, batch, lift, dtype=dtype)
+    x = to_dev(x_np, dtype)
+    ref = plan.forward(x)
+    torch.cuda.synchronize()
+    want = oracle.fft(np.asarray(x.cpu().numpy(), np.complex128))
+    assert rel_err_rows(ref.cpu().numpy(), want) <= tol(n, dtype)
+    outs = [torch.empty_like(x) for _ in range(3)]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.forward(x, out=outs[0])
+        plan.adjoint(outs[0], out=outs[1])
+        plan.forward(x, out=outs[2])
+    for _ in range(4):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], ref) and torch.equal(outs[2], ref)
+        assert torch.equal(outs[1], plan.adjoint(ref))
+        _ = plan.adjoint(x)  # unrelated eager work between replays
+        torch.cuda.synchronize()
