@@ -297,6 +297,9 @@ def extras(args, torch, np, mfft, inputs):
                 xs, ys = xb.cpu().numpy(), ob.cpu().numpy()
                 samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
                                            for i in pick]
+                # The whole batch, for the oracle on all host cores and the
+                # error of every transform.
+                samples["uneven_batch_all"] = {"x": xs, "y": ys, "sizes": sizes, "offsets": offs}
             p.close()
         rec["tuned"]["tuner_ms"] = round(best["ms"], 5)
         # one plain launch per transform (8192 launches, timed once)
@@ -435,6 +438,51 @@ def c128_replay_us(p, x, torch, np, calls=100, replays=20):
         return {"error": f"{type(exc).__name__}: {exc}"}
 
 
+def host_info():
+    """CPU model and core counts of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def oracle_uneven_leg(full, ex, np):
+    """The FP64 oracle over the whole uneven batch on OpenMP threads (the
+    usable cores, at most 16), timed on a buffer already in host memory, and
+    the error of every GPU transform of the batch against it."""
+    import oracle
+    sizes, offs = full["sizes"], full["offsets"]
+    flops = sum(5.0 * s * math.log2(s) for s in sizes)
+    threads = max(1, min(16, host_info()["usable_cores"] or 1))
+    want = full["x"].astype(np.complex128)
+    t0 = time.perf_counter()
+    oracle.fft_packed_inplace(want, sizes, threads=threads)
+    sec = time.perf_counter() - t0
+    y = full["y"].astype(np.complex128)
+    err2 = np.add.reduceat(np.abs(y - want) ** 2, offs[:-1])
+    ref2 = np.add.reduceat(np.abs(want) ** 2, offs[:-1])
+    rel = np.sqrt(err2 / np.maximum(ref2, 1e-300))
+    tol = 2e-6 * np.log2(np.asarray(sizes, np.float64))
+    if ex is not None:
+        ex.setdefault("error_vs_fp64_oracle_all", {})["uneven_batch"] = {
+            "rel_l2_max": float(rel.max()), "max_ratio_to_tolerance": float((rel / tol).max()),
+            "transforms": len(sizes), "pass": bool((rel <= tol).all())}
+    return {"value": round(flops / sec / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "seconds": round(sec, 3),
+            "sample": "the whole uneven batch (%d transforms of 2^6..2^14, %d points), FP64 Van Loan radix-2, "
+                      "OpenMP over the transforms, one run" % (len(sizes), int(offs[-1]))}
+
+
 def cpu_baseline_leg(args, np, result, sample, samples):
     """Time the FP64 oracle on the host (full headline transforms repeated to
     about 10 s, one thread) and state the error of every GPU result against
@@ -458,6 +506,10 @@ def cpu_baseline_leg(args, np, result, sample, samples):
                               "sample": "%d full n=2^%d transforms of the headline input (FP64 Van Loan radix-2, "
                                         "single thread), %.2f s each, %.1f s in all"
                                         % (runs, int(math.log2(n)), per, spent)}
+    result["cpu_baseline"]["host"] = host_info()
+    full = samples.pop("uneven_batch_all", None)
+    if full is not None:
+        result["cpu_baseline"]["uneven_batch"] = oracle_uneven_leg(full, result.get("extras"), np)
     ex = result.get("extras")
     if not ex:
         return

@@ -140,6 +140,18 @@ def fft_packed(x, sizes, sign: int = -1, threads: int = 1) -> np.ndarray:
     return a
 
 
+def fft_packed_inplace(a: np.ndarray, sizes, sign: int = -1, threads: int = 1) -> np.ndarray:
+    """fft_packed on a caller's complex128 C-contiguous buffer, overwritten
+    with the result (no copy: for timing the arithmetic alone)."""
+    if a.dtype != np.complex128 or not a.flags.c_contiguous or not a.flags.writeable:
+        raise ValueError("fft_packed_inplace needs a writeable C-contiguous complex128 array")
+    s = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+    if int(s.sum()) != a.size:
+        raise ValueError("sizes do not sum to the buffer length")
+    _check(_load().moa_or_fft_packed(_ptr(a), _ptr(s), s.size, int(sign), int(threads)), "fft_packed")
+    return a
+
+
 def dft_brute(x, sign: int = -1) -> np.ndarray:
     a = _c128(x)
     y = np.empty_like(a)

@@ -142,6 +142,13 @@ def test_batch_and_packed_agree_with_single():
         off += s
     xb = rand_c(rng, 4 * 128).reshape(4, 128)
     assert np.array_equal(oracle.fft_batch(xb, threads=3), np.stack([oracle.fft(r) for r in xb]))
+    buf = np.array(x, dtype=np.complex128)
+    assert oracle.fft_packed_inplace(buf, sizes, threads=2) is buf
+    assert np.array_equal(buf, got)
+    with pytest.raises(ValueError):
+        oracle.fft_packed_inplace(x.astype(np.complex64), sizes)
+    with pytest.raises(ValueError):
+        oracle.fft_packed_inplace(np.array(x, dtype=np.complex128)[::-1], sizes)
 
 
 def test_rejects_non_power_of_two():
