@@ -152,6 +152,8 @@ def kernel_name(p):
         return "k_pass_mfma<%d, %d>" % (lg, prec)
     if p["kernel_mode"] == 3:
         return "k_pass_pair<%d, %s, %s>" % (lg, tin, tout)
+    if p["kernel_mode"] == 4:
+        return "k_small<%d>" % lg
     return "k_pass<float, %d, %d, %s, %s>" % (lg, p["kernel_mode"], tin, tout)
 
 

@@ -13,6 +13,8 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr int kNoBlock = 30;      // lgb of an axis with one plain stride
 constexpr int kMaxLgBlockC64 = 14;  // 2^14 complex64 = 128 KiB (+pad) in LDS
 constexpr int kMaxLgBlockC128 = 13; // 2^13 complex128
+constexpr int kLgSmallMin = 4;      // one short transform: 2^4 .. 2^12 points
+constexpr int kLgSmallMax = 12;     // on N / 4 threads (fft_small.hip)
 
 // Entries of the in-block twiddle table kept in LDS (two halves of 128).
 constexpr int kTwBlkEntries = 256;
@@ -59,7 +61,8 @@ struct PassDesc {
     int64_t out_s[kMaxDigits] = {0};
     int lgw = 0;                  // log2 transforms per workgroup (tile width)
     int lge = kLgE;               // log2 points per thread
-    int kmode = 0;                // level kernel variant (fft_kernels.hip; 3 = paired columns, fft_pair.hip)
+    int kmode = 0;                // level kernel variant (fft_kernels.hip; 3 = paired columns, fft_pair.hip;
+                                  // 4 = one short transform, fft_small.hip)
     // Inter-level twiddle omega_{2^tw_lgroot}^(d0 * k), d0 = value of digit 0.
     int tw = 0;
     int tw_lgroot = 0;
@@ -154,6 +157,11 @@ const void* mfma_kernel_fn(const PassDesc& d, bool fwd);
 hipError_t launch_pair(const PassDesc& d, const PassArgs& a, hipStream_t s);
 hipError_t prepare_pair_kernel(const PassDesc& d);
 const void* pair_kernel_fn(const PassDesc& d, bool fwd);
+// One short transform (fft_small.hip): a single-level plan of batch one,
+// unit strides, lgn in [kLgSmallMin, kLgSmallMax], kmode 4; N / 4 threads.
+hipError_t launch_small(bool fp64, const PassDesc& d, const PassArgs& a, hipStream_t s);
+hipError_t prepare_small_kernel(bool fp64, const PassDesc& d);
+const void* small_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
 // The kernel function pointers, used to build HIP graph nodes.
 const void* pass_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
 const void* batched_kernel_fn(bool fp64, bool fwd);

@@ -255,6 +255,7 @@ const void* pass_kernel_fn(bool fp64, const PassDesc& d, bool fwd)
 {
     if (d.mfma) return mfma_kernel_fn(d, fwd);
     if (d.kmode == 3) return pair_kernel_fn(d, fwd);
+    if (d.kmode == 4) return small_kernel_fn(fp64, d, fwd);
     return reinterpret_cast<const void*>(pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast));
 }
 
@@ -262,6 +263,7 @@ hipError_t prepare_pass_kernel(bool fp64, const PassDesc& d)
 {
     if (d.mfma) return prepare_mfma_kernel(d);
     if (d.kmode == 3) return prepare_pair_kernel(d);
+    if (d.kmode == 4) return prepare_small_kernel(fp64, d);
     PassFn f = pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -272,6 +274,7 @@ hipError_t launch_pass(bool fp64, const PassDesc& d, const PassArgs& a, hipStrea
 {
     if (d.mfma) return launch_mfma(d, a, s);
     if (d.kmode == 3) return launch_pair(d, a, s);
+    if (d.kmode == 4) return launch_small(fp64, d, a, s);
     PassFn f = pass_fn_lookup(fp64, d.lgn, d.kmode, d.in_tile_fast, d.out_tile_fast);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);

@@ -194,6 +194,25 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
             if ((in_tf && d.in_s[i] % 2) || (out_tf && d.out_s[i] % 2)) return false;
         return true;
     };
+    // One short transform (a single level of batch one, unit strides) is one
+    // workgroup whatever the kernel, so its time is that workgroup's
+    // critical path: the latency kernel (fft_small.hip) spreads it over N / 4
+    // threads of 4 points, radix-4 stages.
+    if (want_w <= 0 && !d.mfma && !d.tw && d.pre_lg == 0 && d.nd == 1 && d.size[0] == 1 && d.in_s_e == 1 &&
+        d.out_s_k == 1 && lgn >= moa::kLgSmallMin && lgn <= moa::kLgSmallMax) {
+        d.lgw = 0;
+        d.lge = 2;
+        d.kmode = 4;
+        d.in_tile_fast = d.out_tile_fast = false;
+        d.col_stride = moa::lds_padded_len(1 << lgn);
+        d.data_elems = d.col_stride;
+        d.lds_bytes = d.data_elems * eb;
+        d.threads = 1 << (lgn - 2);
+        d.blocks = 1;
+        d.grid = 1;
+        d.xcd_remap = 0;
+        return MOA_OK;
+    }
     const int eb0 = int(elem_bytes(fp64));
     auto finish_pair = [&](int lgw_) {
         const int P = 1 << (lgw_ - 1);

@@ -36,8 +36,96 @@ def col_off(w, layout, stride0):
     return (w >> 1) * layout["pair_stride"] + (w & 1) * stride0
 
 
+def check_small(p, total, elem_bytes):
+    """The short-transform kernel: one workgroup of N / 4 threads; thread b
+    loads rows b + r N / 4 and the last stage stores the same rows; every
+    LDS slot of every stage fits the requested LDS."""
+    N = p["N"]
+    assert p["grid"] == p["blocks"] == 1 and p["tile_width"] == 1 and total == N
+    assert p["threads"] == N // 4 and p["points_per_thread"] == 4
+    assert p["dft_axis"]["in_stride"] == 1 and p["dft_axis"]["out_stride"] == 1
+    b = np.arange(N // 4)
+    rows = (b[:, None] + np.arange(4)[None, :] * (N // 4)).ravel()
+    assert np.array_equal(np.sort(rows), np.arange(N))
+    slots = [pad(i) for s_ in small_stage_slots(N) for i in s_]
+    assert (max(slots) + 1) * elem_bytes <= p["lds_bytes"] <= 160 * 1024
+
+
+def small_stage_slots(N):
+    """LDS rows each radix-4 stage of the short-transform kernel writes."""
+    lg = N.bit_length() - 1
+    b = np.arange(N // 4)
+    out = []
+    for s in range(lg // 2):
+        if s + 1 == lg // 2 and lg % 2 == 0:
+            break
+        NS = 1 << (2 * s)
+        base = ((b >> (2 * s)) << (2 * s + 2)) + (b & (NS - 1))
+        out.append((base[:, None] + np.arange(4)[None, :] * NS).ravel())
+    return out
+
+
+def small_model(x, sign=-1):
+    """numpy model of the short-transform kernel's arithmetic order: radix-4
+    Stockham stages (input r of butterfly b is row b + r N / 4, factor
+    omega_{4 NS}^((b mod NS) r), output r to (b / NS) 4 NS + (b mod NS) + r NS),
+    then a radix-2 stage (rows c, c + N / 2, factor omega_N^c) when log2 N is
+    odd."""
+    N = x.size
+    lg = N.bit_length() - 1
+    Q = N // 4
+    b = np.arange(Q)
+    cur = x.astype(np.complex128)
+    for s in range(lg // 2):
+        NS = 1 << (2 * s)
+        v = np.stack([cur[b + r * Q] for r in range(4)])
+        k = b & (NS - 1)
+        for r in range(1, 4):
+            v[r] *= np.exp(sign * 2j * np.pi * k * r / (4 * NS))
+        X = np.stack([sum(v[q] * np.exp(sign * 2j * np.pi * q * r / 4) for q in range(4)) for r in range(4)])
+        base = ((b >> (2 * s)) << (2 * s + 2)) + k
+        nxt = np.empty_like(cur)
+        for r in range(4):
+            nxt[base + r * NS] = X[r]
+        cur = nxt
+    if lg % 2:
+        c = np.arange(N // 2)
+        t = cur[c + N // 2] * np.exp(sign * 2j * np.pi * c / N)
+        cur = np.concatenate([cur[c] + t, cur[c] - t])
+    return cur
+
+
+@pytest.mark.parametrize("lg", range(4, 13))
+def test_short_transform_model_is_the_dft(lg):
+    """The short kernel's stage order and indices compute the DFT (both
+    directions), for every size it serves."""
+    rng = np.random.default_rng(lg)
+    x = rng.uniform(-1, 1, 1 << lg) + 1j * rng.uniform(-1, 1, 1 << lg)
+    assert np.abs(small_model(x) - np.fft.fft(x)).max() <= 1e-12 * (1 << lg)
+    assert np.abs(small_model(x, +1) - np.fft.ifft(x) * x.size).max() <= 1e-12 * (1 << lg)
+
+
+@pytest.mark.parametrize("n,dtype", [(16, capi.MOA_C64), (32, capi.MOA_C128), (1024, capi.MOA_C128),
+                                     (2048, capi.MOA_C64), (4096, capi.MOA_C128), (4096, capi.MOA_C64)])
+def test_short_transform_kernel_selected(n, dtype):
+    """A single short transform of batch one takes the latency kernel; a
+    batch, a lifted plan or a tuned tile width does not."""
+    def modes(batch, lift=None, tuning=None):
+        h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST, tuning=tuning)
+        try:
+            return [q["kernel_mode"] for q in json.loads(capi.moa_fft_describe(h))["passes"]]
+        finally:
+            capi.moa_fft_destroy(h)
+    assert modes(1) == [4]
+    assert 4 not in modes(2)
+    assert 4 not in modes(1, [4, n // 4])
+    assert 4 not in modes(1, tuning={"cols_per_block": [1]})
+
+
 def check_pass(p, total, elem_bytes):
     N = p["N"]
+    if p["kernel_mode"] == 4:
+        return check_small(p, total, elem_bytes)
     mfma = p["mfma"] != "none"
     pair = p["kernel_mode"] == 3
     E = min(N, p["points_per_thread"]) if not mfma else 1
@@ -162,6 +250,8 @@ def check_pass(p, total, elem_bytes):
     (1 << 20, 2, [4096, 256], capi.MOA_C64), (1 << 16, 4, [16, 4096], capi.MOA_C64),
     (1 << 21, 1, [8192, 256], capi.MOA_C64), (1 << 22, 1, [16384, 256], capi.MOA_C64),
     (1 << 21, 1, [256, 8192], capi.MOA_C64),
+    (16, 1, None, capi.MOA_C64), (32, 1, None, capi.MOA_C128), (2048, 1, None, capi.MOA_C64),
+    (4096, 1, None, capi.MOA_C128),
 ])
 def test_pass_kernel_geometry(n, batch, lift, dtype):
     h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST)
