@@ -15,9 +15,18 @@ constexpr int kMaxLgBlockC64 = 14;  // 2^14 complex64 = 128 KiB (+pad) in LDS
 constexpr int kMaxLgBlockC128 = 13; // 2^13 complex128
 constexpr int kLgSmallMin = 4;      // one short transform: 2^4 .. 2^12 points
 constexpr int kLgSmallMax = 12;     // on N / 4 threads (fft_small.hip)
+constexpr int kLgSmallMaxC128 = 11; // complex128 2^12: the level kernel is faster
+constexpr int kLgSmallDirect = 8;   // up to 2^8 points the kernel builds a table of omega_N
 
 // Entries of the in-block twiddle table kept in LDS (two halves of 128).
 constexpr int kTwBlkEntries = 256;
+
+// LDS twiddle entries of the short-transform kernel: omega_N^e for e < N up
+// to 2^kLgSmallDirect points, else a copy of the in-block table.
+__host__ __device__ constexpr inline int small_table_entries(int lgn)
+{
+    return lgn <= kLgSmallDirect ? (1 << lgn) : kTwBlkEntries;
+}
 
 // Elements each thread keeps in registers across a pass (the radix of the
 // register-resident stages) is 2^lge, lge = 4 or 5; a transform shorter than

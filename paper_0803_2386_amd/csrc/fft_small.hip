@@ -11,9 +11,8 @@
 // decimation as the level kernels (input r of butterfly b of a stage that
 // follows NS points' worth of earlier radices is row b + r N / R; its output
 // r goes to (b / NS) NS R + (b mod NS) + r NS), so the last stage writes the
-// natural-order result straight to global memory.  Every stage twiddle is
-// read from the in-block table before the first butterfly, so their load
-// latency hides under the data loads.
+// natural-order result straight to global memory.  The stage twiddles come
+// from LDS tables filled behind the data loads.
 #include "fft_device.h"
 
 namespace moa {
@@ -29,6 +28,8 @@ __global__ void __launch_bounds__(1024) k_small(PassArgs a)
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* col = reinterpret_cast<V*>(smem_raw);
+    V* tab = col + lds_padded_len(N);  // small_table_entries(LGN) twiddles
+    constexpr bool DIRECT = LGN <= kLgSmallDirect;
     const V* in = static_cast<const V*>(a.in);
     V* out = static_cast<V*>(a.out);
     const V* tb = static_cast<const V*>(a.tw_blk);
@@ -37,28 +38,31 @@ __global__ void __launch_bounds__(1024) k_small(PassArgs a)
     V v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) v[r] = in[b + r * Q];
-
-    // Stage s >= 1 multiplies input r by omega_{4 NS}^((b mod NS) r), NS = 4^s.
-    V w[NR4 > 1 ? NR4 - 1 : 1][3];
+    // Every twiddle of the transform is a power of omega_N.  A short one
+    // builds that table in LDS from the in-block table (four entries a
+    // thread, one product each: the rounding the level kernels' twiddles
+    // carry); a longer one copies the 256-entry in-block table itself (at
+    // most two entries a thread) and forms each twiddle as one product.
+    // Either goes to LDS behind the data loads, and the first exchange
+    // barrier publishes it before any stage reads it.
+    if constexpr (DIRECT) {
 #pragma unroll
-    for (int s = 1; s < NR4; ++s) {
-        const int e1 = (b & ((1 << (2 * s)) - 1)) << (kLgTwBlk - 2 * s - 2);
+        for (int r = 0; r < 4; ++r) tab[b + r * Q] = tw_blk(tb, (b + r * Q) << (kLgTwBlk - LGN));
+    } else {
 #pragma unroll
-        for (int r = 1; r < 4; ++r) w[s - 1][r - 1] = tw_blk(tb, e1 * r);
+        for (int i = b; i < kTwBlkEntries; i += Q) tab[i] = tb[i];
     }
-    // The radix-2 stage multiplies the second input of butterfly c by omega_N^c.
-    V w2[2];
-    if constexpr (R2) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) w2[h] = tw_blk(tb, (b + h * Q) << (kLgTwBlk - LGN));
-    }
+    // omega_N^e for e < N.
+    auto tw = [&](int e) { return DIRECT ? tab[e] : tw_blk(tab, e << (kLgTwBlk - LGN)); };
 
 #pragma unroll
     for (int s = 0; s < NR4; ++s) {
         const int NS = 1 << (2 * s);
         if (s > 0) {
+            // Input r times omega_{4 NS}^((b mod NS) r) = omega_N^((b mod NS) r N / (4 NS)).
+            const int e1 = (b & (NS - 1)) << (LGN - 2 * s - 2);
 #pragma unroll
-            for (int r = 1; r < 4; ++r) v[r] = cmul_dir<FWD>(v[r], w[s - 1][r - 1]);
+            for (int r = 1; r < 4; ++r) v[r] = cmul_dir<FWD>(v[r], tw(e1 * r));
         }
         dft4<FWD>(v[0], v[1], v[2], v[3]);
         if (s + 1 == NR4 && !R2) {
@@ -77,9 +81,10 @@ __global__ void __launch_bounds__(1024) k_small(PassArgs a)
     }
     if constexpr (R2) {
         // Butterflies b and b + Q take rows (b, b + 2Q) and (b + Q, b + 3Q),
-        // i.e. v[0], v[2] and v[1], v[3]; outputs c and c + N / 2.
-        const V x = cmul_dir<FWD>(v[2], w2[0]);
-        const V y = cmul_dir<FWD>(v[3], w2[1]);
+        // i.e. v[0], v[2] and v[1], v[3]; the second input of butterfly c is
+        // multiplied by omega_N^c; outputs c and c + N / 2.
+        const V x = cmul_dir<FWD>(v[2], tw(b));
+        const V y = cmul_dir<FWD>(v[3], tw(b + Q));
         out[b] = cadd(v[0], x);
         out[b + 2 * Q] = csub(v[0], x);
         out[b + Q] = cadd(v[1], y);

@@ -199,14 +199,14 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     // critical path: the latency kernel (fft_small.hip) spreads it over N / 4
     // threads of 4 points, radix-4 stages.
     if (want_w <= 0 && !d.mfma && !d.tw && d.pre_lg == 0 && d.nd == 1 && d.size[0] == 1 && d.in_s_e == 1 &&
-        d.out_s_k == 1 && lgn >= moa::kLgSmallMin && lgn <= moa::kLgSmallMax) {
+        d.out_s_k == 1 && lgn >= moa::kLgSmallMin && lgn <= (fp64 ? moa::kLgSmallMaxC128 : moa::kLgSmallMax)) {
         d.lgw = 0;
         d.lge = 2;
         d.kmode = 4;
         d.in_tile_fast = d.out_tile_fast = false;
         d.col_stride = moa::lds_padded_len(1 << lgn);
         d.data_elems = d.col_stride;
-        d.lds_bytes = d.data_elems * eb;
+        d.lds_bytes = (d.data_elems + moa::small_table_entries(lgn)) * eb;  // exchange tile, then twiddles
         d.threads = 1 << (lgn - 2);
         d.blocks = 1;
         d.grid = 1;

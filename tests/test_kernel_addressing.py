@@ -48,7 +48,11 @@ def check_small(p, total, elem_bytes):
     rows = (b[:, None] + np.arange(4)[None, :] * (N // 4)).ravel()
     assert np.array_equal(np.sort(rows), np.arange(N))
     slots = [pad(i) for s_ in small_stage_slots(N) for i in s_]
-    assert (max(slots) + 1) * elem_bytes <= p["lds_bytes"] <= 160 * 1024
+    # the exchange tile (N padded), then omega_N^e for e < N (N <= 256) or
+    # the 256-entry in-block table
+    table0 = N + (N >> 4)
+    entries = N if N <= 256 else 256
+    assert max(slots) < table0 and (table0 + entries) * elem_bytes == p["lds_bytes"] <= 160 * 1024
 
 
 def small_stage_slots(N):
@@ -81,7 +85,9 @@ def small_model(x, sign=-1):
         v = np.stack([cur[b + r * Q] for r in range(4)])
         k = b & (NS - 1)
         for r in range(1, 4):
-            v[r] *= np.exp(sign * 2j * np.pi * k * r / (4 * NS))
+            e = (k * r) << (lg - 2 * s - 2)  # index into the kernel's table of omega_N
+            assert e.max() < N
+            v[r] *= np.exp(sign * 2j * np.pi * e / N)
         X = np.stack([sum(v[q] * np.exp(sign * 2j * np.pi * q * r / 4) for q in range(4)) for r in range(4)])
         base = ((b >> (2 * s)) << (2 * s + 2)) + k
         nxt = np.empty_like(cur)
@@ -106,10 +112,11 @@ def test_short_transform_model_is_the_dft(lg):
 
 
 @pytest.mark.parametrize("n,dtype", [(16, capi.MOA_C64), (32, capi.MOA_C128), (1024, capi.MOA_C128),
-                                     (2048, capi.MOA_C64), (4096, capi.MOA_C128), (4096, capi.MOA_C64)])
+                                     (2048, capi.MOA_C64), (2048, capi.MOA_C128), (4096, capi.MOA_C64)])
 def test_short_transform_kernel_selected(n, dtype):
-    """A single short transform of batch one takes the latency kernel; a
-    batch, a lifted plan or a tuned tile width does not."""
+    """A single short transform of batch one takes the latency kernel (up to
+    2^12 points complex64, 2^11 complex128); a batch, a lifted plan or a
+    tuned tile width does not."""
     def modes(batch, lift=None, tuning=None):
         h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST, tuning=tuning)
         try:
@@ -118,6 +125,12 @@ def test_short_transform_kernel_selected(n, dtype):
             capi.moa_fft_destroy(h)
     assert modes(1) == [4]
     assert 4 not in modes(2)
+    if dtype == capi.MOA_C128:
+        h = capi.moa_fft_plan(4096, 1, None, dtype=dtype, flags=HOST)
+        try:
+            assert json.loads(capi.moa_fft_describe(h))["passes"][0]["kernel_mode"] != 4
+        finally:
+            capi.moa_fft_destroy(h)
     assert 4 not in modes(1, [4, n // 4])
     assert 4 not in modes(1, tuning={"cols_per_block": [1]})
 
@@ -251,7 +264,8 @@ def check_pass(p, total, elem_bytes):
     (1 << 21, 1, [8192, 256], capi.MOA_C64), (1 << 22, 1, [16384, 256], capi.MOA_C64),
     (1 << 21, 1, [256, 8192], capi.MOA_C64),
     (16, 1, None, capi.MOA_C64), (32, 1, None, capi.MOA_C128), (2048, 1, None, capi.MOA_C64),
-    (4096, 1, None, capi.MOA_C128),
+    (4096, 1, None, capi.MOA_C128), (2048, 1, None, capi.MOA_C128), (256, 1, None, capi.MOA_C64),
+    (512, 1, None, capi.MOA_C128),
 ])
 def test_pass_kernel_geometry(n, batch, lift, dtype):
     h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST)
