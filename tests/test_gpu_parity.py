@@ -299,3 +299,34 @@ def test_launches_recorded_in_a_caller_graph(n, batch, lift, dtype):
         assert torch.equal(outs[1], plan.adjoint(ref))
         _ = plan.adjoint(x)  # unrelated eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_short_transform_kernel_every_size(dtype):
+    """The latency kernel (one transform, batch one, 2^4..2^12 points; 2^11
+    for complex128): forward and adjoint against the oracle at every size it
+    serves, in place equal to out of place, and within tolerance of the level
+    kernel the planner uses when a tile width is given."""
+    need_gpu()
+    top = 12 if dtype == torch.complex64 else 11
+    for lg in range(4, top + 1):
+        n = 1 << lg
+        x_np = inputs.uniform_complex(n, seed=100 + lg, dtype=np.complex64 if dtype == torch.complex64
+                                      else np.complex128)
+        plan = mfft.Plan(n, 1, None, dtype=dtype)
+        assert plan.describe()["passes"][0]["kernel_mode"] == 4
+        x = to_dev(x_np, dtype)
+        xd = np.asarray(x.cpu().numpy(), np.complex128)
+        for sign, run in ((-1, plan.forward), (1, plan.adjoint)):
+            y = run(x)
+            z = x.clone()
+            run(z, out=z)
+            torch.cuda.synchronize()
+            assert torch.equal(y, z), (lg, sign)
+            assert rel_err_rows(y.cpu().numpy(), oracle.fft(xd, sign)) <= tol(n, dtype), (lg, sign)
+        level = mfft.Plan(n, 1, None, dtype=dtype, tuning={"cols_per_block": [1]})
+        assert level.describe()["passes"][0]["kernel_mode"] != 4
+        ref = level.forward(x).cpu().numpy()
+        assert rel_err_rows(plan.forward(x).cpu().numpy(), ref.astype(np.complex128)) <= 2 * tol(n, dtype)
+        plan.close()
+        level.close()
