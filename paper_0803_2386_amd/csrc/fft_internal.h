@@ -17,6 +17,11 @@ constexpr int kLgSmallMin = 4;      // one short transform: 2^4 .. 2^12 points
 constexpr int kLgSmallMax = 12;     // on N / 4 threads (fft_small.hip)
 constexpr int kLgSmallMaxC128 = 11; // complex128 2^12: the level kernel is faster
 constexpr int kLgSmallDirect = 8;   // up to 2^8 points the kernel builds a table of omega_N
+// A batch of short transforms runs one workgroup per transform while that
+// beats the level kernel's tiles of several transforms: at most 2048
+// transforms and 2^19 points in all (measured crossover 2^19 .. 2^21 points).
+constexpr int64_t kSmallMaxBatch = 2048;
+constexpr int kLgSmallMaxPoints = 19;
 
 // Entries of the in-block twiddle table kept in LDS (two halves of 128).
 constexpr int kTwBlkEntries = 256;

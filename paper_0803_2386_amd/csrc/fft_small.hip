@@ -30,8 +30,9 @@ __global__ void __launch_bounds__(1024) k_small(PassArgs a)
     V* col = reinterpret_cast<V*>(smem_raw);
     V* tab = col + lds_padded_len(N);  // small_table_entries(LGN) twiddles
     constexpr bool DIRECT = LGN <= kLgSmallDirect;
-    const V* in = static_cast<const V*>(a.in);
-    V* out = static_cast<V*>(a.out);
+    // Workgroup k transforms the k-th of a batch of contiguous transforms.
+    const V* in = static_cast<const V*>(a.in) + int64_t(blockIdx.x) * a.in_s[0];
+    V* out = static_cast<V*>(a.out) + int64_t(blockIdx.x) * a.out_s[0];
     const V* tb = static_cast<const V*>(a.tw_blk);
     const int b = threadIdx.x;
 
@@ -128,8 +129,9 @@ hipError_t prepare_small_kernel(bool fp64, const PassDesc& d)
 hipError_t launch_small(bool fp64, const PassDesc& d, const PassArgs& a, hipStream_t s)
 {
     SmallFn f = small_lookup(fp64, d, a.sign < 0.f);
-    if (!f || d.threads != (1 << (d.lgn - 2)) || d.grid != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(1u), dim3(unsigned(d.threads)), d.lds_bytes, s, a);
+    if (!f || d.threads != (1 << (d.lgn - 2)) || d.grid != d.blocks || d.grid < 1 || d.grid > kSmallMaxBatch)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(unsigned(d.grid)), dim3(unsigned(d.threads)), d.lds_bytes, s, a);
     return hipGetLastError();
 }
 

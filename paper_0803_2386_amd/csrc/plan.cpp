@@ -194,12 +194,15 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
             if ((in_tf && d.in_s[i] % 2) || (out_tf && d.out_s[i] % 2)) return false;
         return true;
     };
-    // One short transform (a single level of batch one, unit strides) is one
-    // workgroup whatever the kernel, so its time is that workgroup's
-    // critical path: the latency kernel (fft_small.hip) spreads it over N / 4
-    // threads of 4 points, radix-4 stages.
-    if (want_w <= 0 && !d.mfma && !d.tw && d.pre_lg == 0 && d.nd == 1 && d.size[0] == 1 && d.in_s_e == 1 &&
-        d.out_s_k == 1 && lgn >= moa::kLgSmallMin && lgn <= (fp64 ? moa::kLgSmallMaxC128 : moa::kLgSmallMax)) {
+    // One short transform (a single level, unit strides) is one workgroup
+    // whatever the kernel, so its time is that workgroup's critical path:
+    // the latency kernel (fft_small.hip) spreads it over N / 4 threads of 4
+    // points, radix-4 stages.  A small batch of them runs one such workgroup
+    // per transform.
+    if (want_w <= 0 && !d.mfma && !d.tw && d.pre_lg == 0 && d.nd == 1 && d.size[0] <= moa::kSmallMaxBatch &&
+        (d.size[0] << lgn) <= (int64_t(1) << moa::kLgSmallMaxPoints) &&
+        d.in_s_e == 1 && d.out_s_k == 1 && d.in_s[0] == (int64_t(1) << lgn) && d.out_s[0] == (int64_t(1) << lgn) &&
+        lgn >= moa::kLgSmallMin && lgn <= (fp64 ? moa::kLgSmallMaxC128 : moa::kLgSmallMax)) {
         d.lgw = 0;
         d.lge = 2;
         d.kmode = 4;
@@ -208,8 +211,8 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         d.data_elems = d.col_stride;
         d.lds_bytes = (d.data_elems + moa::small_table_entries(lgn)) * eb;  // exchange tile, then twiddles
         d.threads = 1 << (lgn - 2);
-        d.blocks = 1;
-        d.grid = 1;
+        d.blocks = d.size[0];  // one workgroup a transform
+        d.grid = d.size[0];
         d.xcd_remap = 0;
         return MOA_OK;
     }

@@ -303,10 +303,10 @@ def test_launches_recorded_in_a_caller_graph(n, batch, lift, dtype):
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 def test_short_transform_kernel_every_size(dtype):
-    """The latency kernel (one transform, batch one, 2^4..2^12 points; 2^11
-    for complex128): forward and adjoint against the oracle at every size it
-    serves, in place equal to out of place, and within tolerance of the level
-    kernel the planner uses when a tile width is given."""
+    """The latency kernel (2^4..2^12 points; 2^11 for complex128): forward
+    and adjoint against the oracle at every size it serves, in place equal to
+    out of place, within tolerance of the level kernel the planner uses when a
+    tile width is given, and in batches (one workgroup a transform)."""
     need_gpu()
     top = 12 if dtype == torch.complex64 else 11
     for lg in range(4, top + 1):
@@ -330,3 +330,15 @@ def test_short_transform_kernel_every_size(dtype):
         assert rel_err_rows(plan.forward(x).cpu().numpy(), ref.astype(np.complex128)) <= 2 * tol(n, dtype)
         plan.close()
         level.close()
+    # a batch: one workgroup per transform
+    for lg, B in ((4, 2048), (9, 5), (top, 3)):
+        n = 1 << lg
+        x_np = inputs.uniform_complex((B, n), seed=200 + lg, dtype=np.complex64 if dtype == torch.complex64
+                                      else np.complex128)
+        plan = mfft.Plan(n, B, None, dtype=dtype)
+        assert plan.describe()["passes"][0]["kernel_mode"] == 4 and plan.describe()["passes"][0]["grid"] == B
+        x = to_dev(x_np, dtype)
+        xd = np.asarray(x.cpu().numpy(), np.complex128)
+        assert rel_err_rows(plan.forward(x).cpu().numpy(), oracle.fft(xd)) <= tol(n, dtype), (lg, B)
+        assert rel_err_rows(plan.adjoint(x).cpu().numpy(), oracle.fft(xd, 1)) <= tol(n, dtype), (lg, B)
+        plan.close()

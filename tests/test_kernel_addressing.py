@@ -41,12 +41,16 @@ def check_small(p, total, elem_bytes):
     loads rows b + r N / 4 and the last stage stores the same rows; every
     LDS slot of every stage fits the requested LDS."""
     N = p["N"]
-    assert p["grid"] == p["blocks"] == 1 and p["tile_width"] == 1 and total == N
+    B = total // N
+    ax = p["batch_axes"]
+    assert len(ax) == 1 and ax[0]["size"] == B and ax[0]["in_stride"] == ax[0]["out_stride"] == N
+    assert p["grid"] == p["blocks"] == B and p["tile_width"] == 1 and total == N * B
     assert p["threads"] == N // 4 and p["points_per_thread"] == 4
     assert p["dft_axis"]["in_stride"] == 1 and p["dft_axis"]["out_stride"] == 1
+    # workgroup k, thread b: element k N + b + r N / 4 on load and store
     b = np.arange(N // 4)
-    rows = (b[:, None] + np.arange(4)[None, :] * (N // 4)).ravel()
-    assert np.array_equal(np.sort(rows), np.arange(N))
+    rows = (np.arange(B)[:, None, None] * N + b[None, :, None] + np.arange(4)[None, None, :] * (N // 4)).ravel()
+    assert np.array_equal(np.sort(rows), np.arange(total))
     slots = [pad(i) for s_ in small_stage_slots(N) for i in s_]
     # the exchange tile (N padded), then omega_N^e for e < N (N <= 256) or
     # the 256-entry in-block table
@@ -114,9 +118,10 @@ def test_short_transform_model_is_the_dft(lg):
 @pytest.mark.parametrize("n,dtype", [(16, capi.MOA_C64), (32, capi.MOA_C128), (1024, capi.MOA_C128),
                                      (2048, capi.MOA_C64), (2048, capi.MOA_C128), (4096, capi.MOA_C64)])
 def test_short_transform_kernel_selected(n, dtype):
-    """A single short transform of batch one takes the latency kernel (up to
-    2^12 points complex64, 2^11 complex128); a batch, a lifted plan or a
-    tuned tile width does not."""
+    """A short transform (up to 2^12 points complex64, 2^11 complex128) takes
+    the latency kernel alone or in a batch of at most 2048 transforms and
+    2^19 points; a larger batch, a lifted plan or a tuned tile width does
+    not."""
     def modes(batch, lift=None, tuning=None):
         h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST, tuning=tuning)
         try:
@@ -124,7 +129,10 @@ def test_short_transform_kernel_selected(n, dtype):
         finally:
             capi.moa_fft_destroy(h)
     assert modes(1) == [4]
-    assert 4 not in modes(2)
+    assert modes(2) == [4]
+    big = min(2048, (1 << 19) // n)
+    assert modes(big) == [4]
+    assert 4 not in modes(2 * big)
     if dtype == capi.MOA_C128:
         h = capi.moa_fft_plan(4096, 1, None, dtype=dtype, flags=HOST)
         try:
@@ -265,7 +273,8 @@ def check_pass(p, total, elem_bytes):
     (1 << 21, 1, [256, 8192], capi.MOA_C64),
     (16, 1, None, capi.MOA_C64), (32, 1, None, capi.MOA_C128), (2048, 1, None, capi.MOA_C64),
     (4096, 1, None, capi.MOA_C128), (2048, 1, None, capi.MOA_C128), (256, 1, None, capi.MOA_C64),
-    (512, 1, None, capi.MOA_C128),
+    (512, 1, None, capi.MOA_C128), (16, 2048, None, capi.MOA_C64), (1024, 7, None, capi.MOA_C128),
+    (4096, 128, None, capi.MOA_C64),
 ])
 def test_pass_kernel_geometry(n, batch, lift, dtype):
     h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST)
