@@ -91,7 +91,11 @@ typedef enum {
  * innermost block c, the first pass).  Zero entries select the defaults. */
 typedef struct {
     int32_t cols_per_block[8];  /* transforms (columns of the lifted view)
-                                   handled by one workgroup in that pass   */
+                                   handled by one workgroup in that pass;
+                                   a nonzero entry also selects the level
+                                   kernel for a short single-level plan,
+                                   which by default runs one transform a
+                                   workgroup on N/4 threads              */
     int32_t persistent_blocks;  /* uneven batch: workgroups of the fused
                                    launch (0 = one per task; fewer make it
                                    persistent, each workgroup walking the
