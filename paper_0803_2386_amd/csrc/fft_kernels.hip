@@ -83,8 +83,12 @@ __global__ void __launch_bounds__(mode_threads(KM)) k_pass(PassArgs a)
     }
 
     {
-        const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
-        for (int i = t; i < kTwBlkEntries; i += T) tl[i] = g1[i];
+        // A level of one radix stage has no stage twiddles: it skips the
+        // in-block table (a short level may run on a single thread).
+        if constexpr (n_stages(LGN) > 1) {
+            const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
+            for (int i = t; i < kTwBlkEntries; i += T) tl[i] = g1[i];
+        }
         const V* g2 = reinterpret_cast<const V*>(a.tw_inter);
         for (int i = t; i < 256 * a.tw_parts; i += T) tt[i] = g2[i];
     }
