@@ -540,7 +540,7 @@ def main():
                     help="also run a plain device copy of the same buffer (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the transform runs on one GPU; --gpus {args.gpus} is not supported "
               "(a sharded transform would need an all-to-all exchange between GPUs).", file=sys.stderr)
         sys.exit(2)
 
