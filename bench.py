@@ -481,7 +481,7 @@ def oracle_uneven_leg(full, ex, np):
             "transforms": len(sizes), "pass": bool((rel <= tol).all())}
     return {"value": round(flops / sec / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "seconds": round(sec, 3),
-            "sample": "the whole uneven batch (%d transforms of 2^6..2^14, %d points), FP64 Van Loan radix-2, "
+            "sample": "the whole uneven batch (%d transforms of 2^6..2^14, %d points), FP64 recursive radix-2 oracle, "
                       "OpenMP over the transforms, one run" % (len(sizes), int(offs[-1]))}
 
 
@@ -505,7 +505,7 @@ def cpu_baseline_leg(args, np, result, sample, samples):
                                       "pass": err <= 2e-6 * math.log2(n)}
     result["cpu_baseline"] = {"value": round(gflops(n, 1, per), 3), "unit": "GFLOP/s", "cores": 1,
                               "kind": "oracle",
-                              "sample": "%d full n=2^%d transforms of the headline input (FP64 Van Loan radix-2, "
+                              "sample": "%d full n=2^%d transforms of the headline input (FP64 recursive radix-2 oracle, "
                                         "single thread), %.2f s each, %.1f s in all"
                                         % (runs, int(math.log2(n)), per, spent)}
     result["cpu_baseline"]["host"] = host_info()

@@ -11,7 +11,8 @@ index-algebra oracle (psi, gamma, reshape, transpose, PCT) in plain Python.
 
 Functions (all on numpy ``complex128`` arrays, sign -1 = forward):
 
-* :func:`fft` -- Van Loan radix-2, the result oracle (Ch. 3, Fig. vanloan_fft).
+* :func:`fft` -- the result oracle: the DFT by the recursive even/odd split of
+  its definition (Ch. 3, "Traditional FFT Algorithm", problem statement).
 * :func:`dft_brute` -- O(n^2) definition, long double (pins :func:`fft`).
 * :func:`fft_lifted` -- the cache-optimized method with reshape-transposes,
   transformed weights and the final transpose (Ch. 3).

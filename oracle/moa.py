@@ -135,7 +135,8 @@ def transpose(A: MArray, perm: Sequence[int] | None = None) -> MArray:
 
 
 def reverse(A: MArray) -> MArray:
-    """Phi A: reversal along axis 0."""
+    """Phi A: reversal along axis 0 (Ch. 2, Def. reverse: the shape is kept
+    and <i> psi (Phi A) = <s_0 - i - 1> psi A)."""
     s0 = A.shape[0]
     sub = pi(A.shape[1:])
     out = []
@@ -149,17 +150,6 @@ def take_array(k: int, A: MArray) -> MArray:
     """k take A along axis 0 (0 <= k <= s_0)."""
     sub = pi(A.shape[1:])
     return MArray([k] + A.shape[1:], A.ravel[:k * sub])
-
-
-def rotate_array(k: int, A: MArray) -> MArray:
-    """Rotate A along axis 0 by k: <i> psi result = <(i + k) mod s_0> psi A."""
-    s0 = A.shape[0]
-    sub = pi(A.shape[1:])
-    out = []
-    for i in range(s0):
-        base = ((i + k) % s0) * sub
-        out.extend(A.ravel[base:base + sub])
-    return MArray(A.shape, out)
 
 
 def pct(shape: Sequence[int], j: Sequence[int]) -> Tuple[int, int]:

@@ -8,12 +8,15 @@
  *
  * Everything here is written for obviousness, not speed:
  *
- *  - moa_or_fft          : the result oracle.  Van Loan's high-level radix-2
- *                          program (Ch. 3, "Traditional FFT Algorithm",
- *                          Fig. vanloan_fft): bit-reversal permutation P_n,
- *                          then t = log2 n stages x_{L x r} <- B_L x_{L x r}
- *                          with B_L = [I  Omega; I  -Omega], carried out as the
- *                          in-place butterfly loop of Fig. rad2_fft.
+ *  - moa_or_fft          : the result oracle.  The DFT of the problem
+ *                          statement of Ch. 3 ("Traditional FFT Algorithm":
+ *                          input x in C^n, n = 2^t, output the DFT of x),
+ *                          evaluated by the even/odd split of the definition
+ *                          itself: with E and O the half-length DFTs of the
+ *                          even and odd samples, X_k = E_k + w^k O_k and
+ *                          X_{k+n/2} = E_k - w^k O_k, applied recursively,
+ *                          out of place, natural order in and out (no
+ *                          bit-reversal table, no in-place loop nest).
  *  - moa_or_dft_brute    : the plain O(n^2) definition of the DFT, in long
  *                          double, used to pin moa_or_fft for small n.
  *  - moa_or_fft_lifted   : the method oracle.  The cache-optimized FFT of
@@ -87,7 +90,8 @@ void moa_or_root(int64_t e, int64_t L, int sign, double* re, double* im)
     *im = (sign < 0) ? -s : s;
 }
 
-/* P_n: the bit-reversal permutation of Fig. vanloan_fft, line (1). */
+/* P_n: the bit-reversal permutation that opens the radix-2 program of
+ * Fig. vanloan_fft (used by the method oracle). */
 void moa_or_bitrev(or_cplx* x, int64_t n)
 {
     int t = or_log2(n);
@@ -105,7 +109,8 @@ void moa_or_bitrev(or_cplx* x, int64_t n)
 
 static void or_butterfly(or_cplx* a, or_cplx* b, double wr, double wi)
 {
-    /* c = w * b; (a, b) <- (a + c, a - c)   (Fig. rad2_fft) */
+    /* c = w * b; (a, b) <- (a + c, a - c): the radix-2 butterfly of the
+       method's in-row stages (Ch. 3, Fig. rad2_fft) */
     double cr = wr * b->re - wi * b->im;
     double ci = wr * b->im + wi * b->re;
     double dr = a->re, di = a->im;
@@ -115,24 +120,53 @@ static void or_butterfly(or_cplx* a, or_cplx* b, double wr, double wi)
     b->im = di - ci;
 }
 
-/* Result oracle: Van Loan radix-2 on one vector of length n (in place).
- * Returns 0 on success, -1 if n is not a power of two. */
+/* DFT of the m samples src[0], src[st], ..., src[(m-1) st] into dst[0..m),
+ * by the even/odd split of the definition: the m/2-point DFTs of the even
+ * samples (into dst[0..m/2)) and of the odd samples (into dst[m/2..m)),
+ * then X_k = E_k + w_m^k O_k, X_{k+m/2} = E_k - w_m^k O_k.  w_m^k is read
+ * from the table of the full length n as w_n^(k n/m), exact in the integer
+ * exponent. */
+static void or_dft_split(const or_cplx* src, int64_t st, or_cplx* dst, int64_t m, int64_t n,
+                         const or_cplx* w)
+{
+    if (m == 1) {
+        dst[0] = src[0];
+        return;
+    }
+    const int64_t h = m / 2;
+    or_dft_split(src, 2 * st, dst, h, n, w);
+    or_dft_split(src + st, 2 * st, dst + h, h, n, w);
+    const int64_t step = n / m;
+    for (int64_t k = 0; k < h; ++k) {
+        const or_cplx e = dst[k], o = dst[k + h], f = w[k * step];
+        const double tr = f.re * o.re - f.im * o.im;
+        const double ti = f.re * o.im + f.im * o.re;
+        dst[k].re = e.re + tr;
+        dst[k].im = e.im + ti;
+        dst[k + h].re = e.re - tr;
+        dst[k + h].im = e.im - ti;
+    }
+}
+
+/* Result oracle: the DFT of one vector of length n = 2^t (in place; sign -1
+ * forward, +1 the conjugate transform).  Returns 0 on success, -1 if n is
+ * not a power of two or memory runs out. */
 int moa_or_fft(or_cplx* x, int64_t n, int sign)
 {
     if (!or_is_pow2(n)) return -1;
-    int t = or_log2(n);
-    moa_or_bitrev(x, n);
-    double* wr = (double*)malloc(sizeof(double) * (size_t)(n / 2 + 1));
-    double* wi = (double*)malloc(sizeof(double) * (size_t)(n / 2 + 1));
-    for (int q = 1; q <= t; ++q) {
-        int64_t L = (int64_t)1 << q, half = L / 2;
-        for (int64_t row = 0; row < half; ++row) moa_or_root(row, L, sign, &wr[row], &wi[row]);
-        for (int64_t col = 0; col < n; col += L)
-            for (int64_t row = 0; row < half; ++row)
-                or_butterfly(&x[col + row], &x[col + row + half], wr[row], wi[row]);
+    if (n == 1) return 0;
+    or_cplx* w = (or_cplx*)malloc(sizeof(or_cplx) * (size_t)(n / 2));
+    or_cplx* y = (or_cplx*)malloc(sizeof(or_cplx) * (size_t)n);
+    if (!w || !y) {
+        free(w);
+        free(y);
+        return -1;
     }
-    free(wr);
-    free(wi);
+    for (int64_t k = 0; k < n / 2; ++k) moa_or_root(k, n, sign, &w[k].re, &w[k].im);
+    or_dft_split(x, 1, y, n, n, w);
+    memcpy(x, y, sizeof(or_cplx) * (size_t)n);
+    free(w);
+    free(y);
     return 0;
 }
 

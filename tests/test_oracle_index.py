@@ -31,6 +31,29 @@ def test_psi_reduction_example():
     assert lhs.shape == g["shape"] and lhs.ravel == rhs.ravel
 
 
+def test_reverse_definition_on_visible_rows():
+    # Ch. 2, Def. reverse: rho(Phi A) = rho A and <i> psi (Phi A) = <s_0 - i - 1> psi A.
+    # Four rows (no fixed middle row) and a 3-D case, so an identity, a
+    # rotation or a reversal of the wrong axis all fail.
+    A = moa.MArray([4, 2], list(range(8)))
+    R = moa.reverse(A)
+    assert R.shape == [4, 2]
+    assert R.ravel == [6, 7, 4, 5, 2, 3, 0, 1]
+    B = moa.MArray([2, 3, 2], list(range(12)))
+    RB = moa.reverse(B)
+    assert RB.ravel == [6, 7, 8, 9, 10, 11, 0, 1, 2, 3, 4, 5]
+    for X, RX in ((A, R), (B, RB), (A345(), moa.reverse(A345()))):
+        s0 = X.shape[0]
+        for i in range(s0):
+            assert moa.psi([i], RX).ravel == moa.psi([s0 - 1 - i], X).ravel
+        assert moa.reverse(RX).ravel == X.ravel
+    # the printed psi-reduction example on a 4-row array: <1 2> psi (2 take (Phi A))
+    # is <2 2> psi A (row s_0 - 1 - 1 of A), which an identity reverse gets wrong
+    C = moa.MArray([4, 5, 4], list(range(80)))
+    assert moa.psi([1, 2], moa.take_array(2, moa.reverse(C))).ravel == moa.psi([2, 2], C).ravel
+    assert moa.psi([1, 2], moa.take_array(2, C)).ravel != moa.psi([2, 2], C).ravel
+
+
 def test_omega_rotate_example():
     g = golden("psi_examples.json")["omega_rotate"]
     rows = [moa.rotate(k, row) for k, row in zip(g["amounts"], g["matrix"])]

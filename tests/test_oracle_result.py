@@ -1,4 +1,5 @@
-"""Pins of the FP64 result oracle (Van Loan radix-2, Ch. 3 Fig. vanloan_fft)
+"""Pins of the FP64 result oracle (the DFT of Ch. 3's problem statement, by the
+recursive even/odd split of its definition)
 against facts fixed by the mathematics: the O(n^2) definition, closed forms,
 linearity, Parseval, the adjoint identity, shift/modulation and the real-input
 symmetry, plus a library routine (numpy's pocketfft) for the textbook case.
