@@ -140,6 +140,41 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch,
                                 const moa_fft_tuning_t* tuning);
 
 /*
+ * Plan `batch` contiguous multi-dimensional transforms of an array of shape
+ * dims[0] x ... x dims[rank-1] (row-major: dims[rank-1] is the contiguous
+ * axis): X[k] = sum_j x[j] exp(-2 pi i sum_a j_a k_a / dims[a]) forward, the
+ * conjugate transform for ADJOINT, unnormalised.  The multi-dimensional
+ * extension of the lifted FFT (Ch. 1, "Conclusions for the General Radix
+ * Approach", and Ch. 3, "Conclusions"): the array is the lifted view of its
+ * ravel, and the transform is the levels of that lift with no inter-level
+ * factor between them and no final digit reversal -- one kernel launch per
+ * axis of extent > 1, the contiguous axis first, each a DFT along its axis
+ * with the inner axes as the tile.  The first launch reads `in` and writes
+ * `out`, the others run in place in `out`, so the plan owns no workspace
+ * (in == out is allowed).
+ *
+ * rank: 1..8.  Every extent must be a power of two of at most one
+ * workgroup's block (moa_fft_max_block: 2^14 for MOA_C64, 2^13 for
+ * MOA_C128), and their product at most 2^30.  prec as for moa_fft_plan
+ * (axes whose length is 16, 256 or 4096 run on the matrix cores with a
+ * SPLIT precision).  Errors: MOA_ERR_NULL (out or dims NULL), MOA_ERR_ARG
+ * (rank outside 1..8, unknown or PER_SIZE flag), MOA_ERR_SIZE (an extent
+ * that is not a power of two, too long, or a product above 2^30),
+ * MOA_ERR_BATCH, MOA_ERR_DTYPE, MOA_ERR_LIFT (no kernel takes an axis, e.g.
+ * a matrix-core axis with too few columns), MOA_ERR_ALLOC / MOA_ERR_HIP.
+ * *out is untouched on error.  moa_fft_num_levels reports the launches;
+ * moa_fft_exec_level(l) runs the l-th launch from `in` to `out`.
+ */
+moa_status_t moa_fft_plan_nd(moa_fft_plan_t* out, int32_t rank, const int64_t* dims, int64_t batch,
+                             moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags);
+
+/* moa_fft_plan_nd with explicit launch tuning (one cols_per_block entry per
+ * launch, in launch order; tuning may be NULL). */
+moa_status_t moa_fft_plan_nd_tuned(moa_fft_plan_t* out, int32_t rank, const int64_t* dims, int64_t batch,
+                                   moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags,
+                                   const moa_fft_tuning_t* tuning);
+
+/*
  * Plan an uneven batch: `count` transforms, transform i of length sizes[i]
  * (each a power of two between 1 and 2^14 for MOA_C64, 2^13 for MOA_C128),
  * packed one after the other in input and output (transform i starts at
@@ -162,8 +197,10 @@ moa_status_t moa_fft_plan_batched_tuned(moa_fft_plan_t* out, const int64_t* size
  * Execute a plan in direction dir on device buffers holding batch * n (or
  * sum(sizes)) complex elements.  in == out (in place) is allowed; other
  * overlaps are not.  Asynchronous on `stream` (a hipStream_t, NULL = null
- * stream).  Errors: MOA_ERR_NULL (p, in or out NULL), MOA_ERR_ARG (bad dir),
- * MOA_ERR_STATE (host-only plan), MOA_ERR_HIP (launch failure).
+ * stream).  Errors: MOA_ERR_NULL (p, in or out NULL), MOA_ERR_STATE (p is
+ * not a live plan, or is host-only), MOA_ERR_ARG (bad dir, or a caller
+ * buffer off the 16-byte alignment a paired-column level needs),
+ * MOA_ERR_HIP (launch failure).
  */
 moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out,
                           void* stream);
@@ -171,7 +208,8 @@ moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, v
 /*
  * Run only level `level` of a lifted plan (one kernel launch): level 0 reads
  * `in`, later levels read the plan's workspace; the last level writes
- * `out`, earlier ones the workspace.  Running levels 0..L-1 in order equals
+ * `out`, earlier ones the workspace.  For a multi-dimensional plan level l
+ * is the l-th axis launch and runs from `in` to `out`.  Running levels 0..L-1 in order equals
  * moa_fft_exec.  For timing and inspecting one level of the lift
  * ("The General Algorithm": one level = one pass over memory).  For an
  * uneven batch planned with MOA_FFT_FLAG_PER_SIZE, level g runs the
@@ -205,7 +243,12 @@ moa_status_t moa_fft_describe(moa_fft_plan_t p, char* buf, size_t len);
 moa_status_t moa_fft_describe_size(moa_fft_plan_t p, size_t* bytes);
 
 /* Release the plan and its device resources.  NULL is accepted (no-op).
- * Destroying a plan twice is undefined: the handle is gone after the call. */
+ * The library keeps a registry of live plans: destroying a plan twice, or
+ * passing any non-NULL handle that is not a live plan to this or any other
+ * call, returns MOA_ERR_STATE without touching memory (a NULL handle gives
+ * MOA_ERR_NULL, except here).  A handle is the plan's address,
+ * so a stale handle that equals a newer plan's address names that plan.
+ * Destroying a plan while another thread uses it is the caller's error. */
 moa_status_t moa_fft_destroy(moa_fft_plan_t p);
 
 /* Static, NUL-terminated name of a status code ("MOA_OK", ...). */

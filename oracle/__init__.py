@@ -20,6 +20,7 @@ Functions (all on numpy ``complex128`` arrays, sign -1 = forward):
 * :func:`lifted_exponents` -- the transformed-weight exponents
   sigma + j c^l ("General Weight Sub-Matrices").
 * :func:`fft_batch`, :func:`fft_packed` -- contiguous and uneven batches.
+* :func:`fftn` -- the multi-dimensional DFT, the 1-D oracle along each axis.
 * :func:`weighted_power_loss` -- L = sum_k w_k |F x|_k^2 and its gradient.
 """
 from __future__ import annotations
@@ -151,6 +152,21 @@ def fft_packed_inplace(a: np.ndarray, sizes, sign: int = -1, threads: int = 1) -
         raise ValueError("sizes do not sum to the buffer length")
     _check(_load().moa_or_fft_packed(_ptr(a), _ptr(s), s.size, int(sign), int(threads)), "fft_packed")
     return a
+
+
+def fftn(x, rank: int, sign: int = -1) -> np.ndarray:
+    """DFT over the last `rank` axes: X[k] = sum_j x[j] exp(sign 2 pi i sum_a
+    j_a k_a / n_a).  The exponential factorises over the axes, so the
+    transform is the 1-D result oracle along each axis in turn -- the
+    multi-dimensional FFT built from the one-dimensional one (Ch. 1,
+    "Conclusions for the General Radix Approach", footnote)."""
+    a = _c128(x).copy()
+    if rank < 1 or rank > a.ndim:
+        raise ValueError("rank must be between 1 and x.ndim")
+    for ax in range(a.ndim - rank, a.ndim):
+        moved = np.ascontiguousarray(np.moveaxis(a, ax, -1))
+        a = np.moveaxis(fft(moved, sign), -1, ax)
+    return np.ascontiguousarray(a)
 
 
 def dft_brute(x, sign: int = -1) -> np.ndarray:

@@ -38,7 +38,8 @@ MOA_FFT_FLAG_PER_SIZE = 0x2
 MOA_FFT_FLAG_GRAPH = 0x4
 
 EXPORTED = [
-    "moa_fft_plan", "moa_fft_plan_tuned", "moa_fft_plan_batched", "moa_fft_plan_batched_tuned",
+    "moa_fft_plan", "moa_fft_plan_tuned", "moa_fft_plan_nd", "moa_fft_plan_nd_tuned",
+    "moa_fft_plan_batched", "moa_fft_plan_batched_tuned",
     "moa_fft_exec", "moa_fft_exec_level", "moa_fft_num_levels", "moa_fft_workspace_size", "moa_fft_describe", "moa_fft_describe_size",
     "moa_fft_destroy", "moa_fft_status_string", "moa_fft_max_block",
 ]
@@ -81,6 +82,8 @@ def load() -> ctypes.CDLL:
     sig = {
         "moa_fft_plan": ([PP, I64, I64, I64P, I32, E, E, U32], E),
         "moa_fft_plan_tuned": ([PP, I64, I64, I64P, I32, E, E, U32, TP], E),
+        "moa_fft_plan_nd": ([PP, I32, I64P, I64, E, E, U32], E),
+        "moa_fft_plan_nd_tuned": ([PP, I32, I64P, I64, E, E, U32, TP], E),
         "moa_fft_plan_batched": ([PP, I64P, I64, E, U32], E),
         "moa_fft_plan_batched_tuned": ([PP, I64P, I64, E, U32, TP], E),
         "moa_fft_exec": ([P, E, P, P, P], E),
@@ -141,6 +144,22 @@ def moa_fft_plan(n, batch=1, lift_shape=None, dtype=MOA_C64, prec=MOA_FFT_PREC_N
                                     int(flags), _tuning(tuning))
     if st != MOA_OK:
         raise MoaError(st, "moa_fft_plan")
+    return h
+
+
+def moa_fft_plan_nd(dims, batch=1, dtype=MOA_C64, prec=MOA_FFT_PREC_NATIVE, flags=0,
+                    tuning=None) -> ctypes.c_void_p:
+    """Multi-dimensional plan of shape dims (row-major); raises MoaError."""
+    lib = load()
+    h = ctypes.c_void_p()
+    arr, rank = _i64_array(dims)
+    if tuning is None:
+        st = lib.moa_fft_plan_nd(ctypes.byref(h), rank, arr, int(batch), int(dtype), int(prec), int(flags))
+    else:
+        st = lib.moa_fft_plan_nd_tuned(ctypes.byref(h), rank, arr, int(batch), int(dtype), int(prec),
+                                       int(flags), _tuning(tuning))
+    if st != MOA_OK:
+        raise MoaError(st, "moa_fft_plan_nd")
     return h
 
 

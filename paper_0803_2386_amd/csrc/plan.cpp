@@ -12,6 +12,7 @@
 #include <new>
 #include <string>
 #include <tuple>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/moa_fft.h"
@@ -78,6 +79,7 @@ struct moa_fft_plan_s {
     int64_t n = 0, batch = 0, total = 0;  // total = complex elements per buffer
     std::vector<int64_t> lift;            // as given: outermost first
     std::vector<int64_t> levels;          // f_0 (innermost, first pass) ...
+    std::vector<int64_t> dims;            // multi-dimensional plan: the array shape (row-major); empty for 1-D
     std::vector<PassDesc> passes;
     // uneven batch
     std::vector<int64_t> sizes;
@@ -327,7 +329,7 @@ void push_digit(PassDesc& d, int64_t size, int64_t in_s, int64_t out_s)
 // stores column pairs with 16-byte accesses.
 void pair_block_workspace(moa_fft_plan_s* p)
 {
-    if (p->passes.size() != 2 || p->fp64 || p->prec != MOA_FFT_PREC_NATIVE) return;
+    if (p->passes.size() != 2 || p->fp64 || p->prec != MOA_FFT_PREC_NATIVE || !p->dims.empty()) return;
     PassDesc& l0 = p->passes[0];
     PassDesc& l1 = p->passes[1];
     if (l0.kmode != 3 || l1.kmode != 3 || l0.mfma || l1.mfma) return;
@@ -394,6 +396,69 @@ moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         p->passes.push_back(d);
     }
     pair_block_workspace(p);
+    return MOA_OK;
+}
+
+// Lower a multi-dimensional transform (Ch. 1, "Conclusions for the General
+// Radix Approach", and Ch. 3, "Conclusions": the lift extends to several
+// dimensions).  The array of shape <n_0 ... n_{k-1}> (row-major) is already
+// the lifted view of its ravel; its DFT is the 1-D DFT along every axis in
+// turn, i.e. the levels of a lift with no inter-level factor between them
+// and no digit reversal at the end.  Axis a (stride S_a = pi(drop(a+1, dims)),
+// O_a = pi(take(a, dims)) outer values) becomes one pass: the DFT of length
+// n_a at stride S_a for every value of the inner axes (digit 0, unit stride:
+// the tile digit, so the tile reads and writes runs along the contiguous
+// axes) and of the outer axes with the batch (one digit of stride n_a S_a).
+// The contiguous last axis runs first, then the others outwards; every pass
+// stores in its load pattern, so after the first pass (in -> out) the rest
+// run in place in out and the plan needs no workspace.
+moa_status_t lower_nd(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
+{
+    const int k = int(p->dims.size());
+    const psi::Vec D(p->dims.begin(), p->dims.end());
+    const psi::Vec S = psi::axis_strides(D);  // stride of each axis
+    const int64_t B = p->batch;
+    p->passes.clear();
+    p->levels.clear();
+    int done_lg = 0;  // log2 of the points transformed by earlier passes
+    for (int a = k - 1; a >= 0; --a) {
+        const int64_t na = D[size_t(a)];
+        if (na == 1) continue;
+        const int64_t Sa = S[size_t(a)];
+        const int64_t outer = psi::pi(psi::take(a, D)) * B;
+        PassDesc d;
+        d.lgn = lg2(na);
+        d.in_s_e = d.out_s_k = Sa;
+        if (Sa > 1) {
+            push_digit(d, Sa, 1, 1);
+            if (outer > 1) push_digit(d, outer, na * Sa, na * Sa);
+        } else {
+            push_digit(d, outer, na, na);
+        }
+        d.tw = 0;
+        d.pre_lg = done_lg;
+        if (p->prec != MOA_FFT_PREC_NATIVE && d.lgn % 4 == 0 && d.lgn >= 4 && d.lgn <= 12) d.mfma = p->prec;
+        const int l = int(p->passes.size());
+        const int want = tuning ? tuning->cols_per_block[l] : 0;
+        if (want < 0) return MOA_ERR_TUNING;
+        moa_status_t st = finish_pass(d, p->fp64, want, p->cus);
+        if (st != MOA_OK) return st;
+        p->passes.push_back(d);
+        p->levels.push_back(na);
+        done_lg += d.lgn;
+    }
+    if (p->passes.empty()) {
+        // Every extent is 1: the transform is the identity, one pass of
+        // length-1 transforms copies in to out.
+        PassDesc d;
+        d.lgn = 0;
+        d.in_s_e = d.out_s_k = 1;
+        push_digit(d, B, 1, 1);
+        moa_status_t st = finish_pass(d, p->fp64, tuning ? tuning->cols_per_block[0] : 0, p->cus);
+        if (st != MOA_OK) return st;
+        p->passes.push_back(d);
+        p->levels.push_back(1);
+    }
     return MOA_OK;
 }
 
@@ -465,7 +530,34 @@ void release(moa_fft_plan_s* p)
     p->d_tables = p->d_ws = p->d_tasks = p->d_toff = nullptr;
 }
 
-bool valid_plan(moa_fft_plan_t p) { return p && p->magic == kMagic; }
+// Live plans.  A handle is valid from its constructor's success until its
+// moa_fft_destroy; calls on any other pointer (a destroyed plan, a stray
+// address) return an error instead of reading freed memory.
+std::mutex& registry_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+std::unordered_set<const void*>& registry()
+{
+    static std::unordered_set<const void*> live;
+    return live;
+}
+
+bool valid_plan(moa_fft_plan_t p)
+{
+    if (!p) return false;
+    std::lock_guard<std::mutex> lock(registry_mutex());
+    return registry().count(p) != 0;
+}
+
+// Status of a handle argument: MOA_ERR_NULL for NULL, MOA_ERR_STATE for a
+// pointer that is not a live plan.
+moa_status_t check_plan(moa_fft_plan_t p)
+{
+    if (!p) return MOA_ERR_NULL;
+    return valid_plan(p) ? MOA_OK : MOA_ERR_STATE;
+}
 
 moa_status_t check_common(moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags)
 {
@@ -487,6 +579,14 @@ moa_status_t finalize(moa_fft_plan_s* p, moa_fft_plan_t* out)
             return st;
         }
     }
+    try {
+        std::lock_guard<std::mutex> lock(registry_mutex());
+        registry().insert(p);
+    } catch (...) {
+        release(p);
+        delete p;
+        return MOA_ERR_ALLOC;
+    }
     *out = p;
     return MOA_OK;
 }
@@ -503,13 +603,17 @@ std::string describe_json(const moa_fft_plan_s* p)
         s += b;
     };
     add("{\"kind\":\"%s\",\"dtype\":\"%s\",\"prec\":\"%s\",\"n\":%lld,\"batch\":%lld,\"elements\":%lld,",
-        p->batched ? "uneven_batch" : "lifted", p->fp64 ? "c128" : "c64",
+        p->batched ? "uneven_batch" : (p->dims.empty() ? "lifted" : "nd"), p->fp64 ? "c128" : "c64",
         p->prec == MOA_FFT_PREC_NATIVE ? "native" : (p->prec == MOA_FFT_PREC_SPLIT_BF16 ? "split_bf16" : "split_fp16"),
         (long long)p->n, (long long)p->batch, (long long)p->total);
     add("\"host_only\":%s,\"workspace_bytes\":%zu,\"stream\":%s,", p->host_only ? "true" : "false",
         p->ws_bytes, p->stream ? "true" : "false");
     s += "\"lift\":[";
     for (size_t i = 0; i < p->lift.size(); ++i) add("%s%lld", i ? "," : "", (long long)p->lift[i]);
+    if (!p->dims.empty()) {
+        s += "],\"dims\":[";
+        for (size_t i = 0; i < p->dims.size(); ++i) add("%s%lld", i ? "," : "", (long long)p->dims[i]);
+    }
     s += "],\"levels\":[";
     for (size_t i = 0; i < p->levels.size(); ++i) add("%s%lld", i ? "," : "", (long long)p->levels[i]);
     s += "],\"passes\":[";
@@ -518,7 +622,8 @@ std::string describe_json(const moa_fft_plan_s* p)
         const bool last = l + 1 == p->passes.size();
         add("%s{\"level\":%zu,\"N\":%lld,\"in\":\"%s\",\"out\":\"%s\",\"dft_axis\":{\"in_stride\":%lld,"
             "\"out_stride\":%lld},\"batch_axes\":[",
-            l ? "," : "", l, (long long)(int64_t(1) << d.lgn), l == 0 ? "x" : "workspace", last ? "y" : "workspace",
+            l ? "," : "", l, (long long)(int64_t(1) << d.lgn), l == 0 ? "x" : (p->dims.empty() ? "workspace" : "y"),
+            (last || !p->dims.empty()) ? "y" : "workspace",
             (long long)d.in_s_e, (long long)d.out_s_k);
         for (int i = 0; i < d.nd; ++i)
             add("%s{\"size\":%lld,\"in_stride\":%lld,\"out_stride\":%lld}", i ? "," : "",
@@ -556,7 +661,7 @@ std::string describe_json(const moa_fft_plan_s* p)
 }
 
 moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, GraphEntry& g);
-moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, hipStream_t s);
+moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, void* ws, hipStream_t s);
 
 // Fill the kernel argument blocks of every pass for one execution.
 // Streaming (non-temporal) access to data a transform touches once: the
@@ -578,18 +683,29 @@ moa_status_t stream_choice(const moa_fft_tuning_t* tuning, size_t in_bytes, bool
     return MOA_OK;
 }
 
-void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, std::vector<moa::PassArgs>& args)
+// Buffers of the passes: a lifted 1-D plan reads `in` on level 0, runs its
+// middle levels in place in the workspace `ws` and writes `out` on its last
+// level; a multi-dimensional plan transforms one axis a pass, `in` -> `out`
+// first, then in place in `out`.
+void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, void* ws,
+               std::vector<moa::PassArgs>& args)
 {
     const size_t eb = elem_bytes(p->fp64);
     const unsigned char* tb = static_cast<const unsigned char*>(p->d_tables);
     args.clear();
     const size_t P = p->passes.size();
+    const bool nd = !p->dims.empty();
     for (size_t l = 0; l < P; ++l) {
         const PassDesc& d = p->passes[l];
         moa::PassArgs a;
         memset(&a, 0, sizeof(a));
-        a.in = l == 0 ? in : p->d_ws;
-        a.out = (l + 1 == P) ? out : p->d_ws;
+        if (nd) {
+            a.in = l == 0 ? in : out;
+            a.out = out;
+        } else {
+            a.in = l == 0 ? in : ws;
+            a.out = (l + 1 == P) ? out : ws;
+        }
         a.in_s_e = d.in_s_e;
         a.out_s_k = d.out_s_k;
         for (int i = 0; i < moa::kMaxDigits; ++i) {
@@ -647,7 +763,7 @@ moa::BatchArgs batch_args(const moa_fft_plan_s* p, int dir, const void* in, void
     return a;
 }
 
-moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, hipStream_t s)
+moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, void* ws, hipStream_t s)
 {
     if (p->batched) {
         if (p->flags & MOA_FFT_FLAG_PER_SIZE) {
@@ -664,7 +780,7 @@ moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, h
         return MOA_OK;
     }
     std::vector<moa::PassArgs> args;
-    pass_args(p, dir, in, out, args);
+    pass_args(p, dir, in, out, ws, args);
     for (size_t l = 0; l < p->passes.size(); ++l)
         if (moa::launch_pass(p->fp64, p->passes[l], args[l], s) != hipSuccess) return MOA_ERR_HIP;
     return MOA_OK;
@@ -712,7 +828,7 @@ moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, G
         }
     } else {
         std::vector<moa::PassArgs> args;
-        pass_args(p, dir, in, out, args);
+        pass_args(p, dir, in, out, p->d_ws, args);
         for (size_t l = 0; l < p->passes.size() && st == MOA_OK; ++l) {
             const PassDesc& d = p->passes[l];
             st = add_node(g.graph, &prev, moa::pass_kernel_fn(p->fp64, d, dir == MOA_FFT_FORWARD), dim3(unsigned(d.grid)),
@@ -898,6 +1014,59 @@ moa_status_t moa_fft_plan(moa_fft_plan_t* out, int64_t n, int64_t batch, const i
     return moa_fft_plan_tuned(out, n, batch, lift_shape, lift_rank, dtype, prec, flags, nullptr);
 }
 
+moa_status_t moa_fft_plan_nd_tuned(moa_fft_plan_t* out, int32_t rank, const int64_t* dims, int64_t batch,
+                                   moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags,
+                                   const moa_fft_tuning_t* tuning)
+{
+    if (!out || !dims) return MOA_ERR_NULL;
+    moa_status_t st = check_common(dtype, prec, flags);
+    if (st != MOA_OK) return st;
+    if (flags & MOA_FFT_FLAG_PER_SIZE) return MOA_ERR_ARG;
+    if (rank < 1 || rank > 8) return MOA_ERR_ARG;
+    const bool fp64 = dtype == MOA_C128;
+    const int maxlg = max_lg_block(fp64);
+    int64_t n = 1;
+    for (int i = 0; i < rank; ++i) {
+        if (!is_pow2(dims[i]) || lg2(dims[i]) > maxlg) return MOA_ERR_SIZE;
+        n *= dims[i];
+        if (lg2(n) > kLgMaxN) return MOA_ERR_SIZE;
+    }
+    if (batch < 1) return MOA_ERR_BATCH;
+    if (n > (int64_t(1) << 40) / batch) return MOA_ERR_BATCH;
+    moa_fft_plan_s* p = new (std::nothrow) moa_fft_plan_s();
+    if (!p) return MOA_ERR_ALLOC;
+    p->fp64 = fp64;
+    p->prec = prec;
+    p->flags = flags;
+    p->host_only = (flags & MOA_FFT_FLAG_HOST_ONLY) != 0;
+    p->n = n;
+    p->batch = batch;
+    p->total = n * batch;
+    p->dims.assign(dims, dims + rank);
+    p->lift = p->dims;
+    if (!p->host_only) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->cus = cus;
+    }
+    st = lower_nd(p, tuning);
+    if (st == MOA_OK) st = stream_choice(tuning, size_t(p->total) * elem_bytes(fp64), p->stream);
+    if (st != MOA_OK) {
+        delete p;
+        return st;
+    }
+    build_tables(p);
+    p->ws_bytes = 0;
+    return finalize(p, out);
+}
+
+moa_status_t moa_fft_plan_nd(moa_fft_plan_t* out, int32_t rank, const int64_t* dims, int64_t batch,
+                             moa_fft_dtype_t dtype, moa_fft_prec_t prec, uint32_t flags)
+{
+    return moa_fft_plan_nd_tuned(out, rank, dims, batch, dtype, prec, flags, nullptr);
+}
+
 moa_status_t moa_fft_plan_batched_tuned(moa_fft_plan_t* out, const int64_t* sizes, int64_t count,
                                         moa_fft_dtype_t dtype, uint32_t flags, const moa_fft_tuning_t* tuning)
 {
@@ -932,7 +1101,7 @@ moa_status_t moa_fft_plan_batched(moa_fft_plan_t* out, const int64_t* sizes, int
 
 // Paired-column levels move column pairs with 16-byte accesses on their
 // unit-stride side; a caller buffer on that side must be 16-byte aligned.
-bool pair_aligned(const PassDesc& d, const void* in, const void* out, bool reads_in, bool writes_out)
+static bool pair_aligned(const PassDesc& d, const void* in, const void* out, bool reads_in, bool writes_out)
 {
     if (d.kmode != 3) return true;
     if (reads_in && d.in_tile_fast && (reinterpret_cast<uintptr_t>(in) & 15u)) return false;
@@ -940,15 +1109,30 @@ bool pair_aligned(const PassDesc& d, const void* in, const void* out, bool reads
     return true;
 }
 
+// Every pass's caller buffers meet the paired-column alignment: a 1-D plan
+// reads `in` on level 0 and writes `out` on its last level; a
+// multi-dimensional plan reads `in` on its first pass and `out` after it,
+// and writes `out` on every pass.
+static bool exec_aligned(const moa_fft_plan_s* p, const void* in, const void* out)
+{
+    const size_t P = p->passes.size();
+    for (size_t l = 0; l < P; ++l) {
+        const bool ok = p->dims.empty() ? pair_aligned(p->passes[l], in, out, l == 0, l + 1 == P)
+                                        : pair_aligned(p->passes[l], l == 0 ? in : out, out, true, true);
+        if (!ok) return false;
+    }
+    return true;
+}
+
 moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out, void* stream)
 {
-    if (!valid_plan(p) || !in || !out) return MOA_ERR_NULL;
+    if (const moa_status_t hs = check_plan(p)) return hs;
+    if (!in || !out) return MOA_ERR_NULL;
     if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
     if (p->host_only) return MOA_ERR_STATE;
-    for (size_t l = 0; l < p->passes.size(); ++l)
-        if (!pair_aligned(p->passes[l], in, out, l == 0, l + 1 == p->passes.size())) return MOA_ERR_ARG;
+    if (!exec_aligned(p, in, out)) return MOA_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!(p->flags & MOA_FFT_FLAG_GRAPH)) return launch_all(p, int(dir), in, out, s);
+    if (!(p->flags & MOA_FFT_FLAG_GRAPH)) return launch_all(p, int(dir), in, out, p->d_ws, s);
     std::lock_guard<std::mutex> lock(p->mu);
     GraphEntry* hit = nullptr;
     for (GraphEntry& g : p->graphs)
@@ -972,7 +1156,8 @@ moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, v
 moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t level, const void* in, void* out,
                                 void* stream)
 {
-    if (!valid_plan(p) || !in || !out) return MOA_ERR_NULL;
+    if (const moa_status_t hs = check_plan(p)) return hs;
+    if (!in || !out) return MOA_ERR_NULL;
     if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
     if (p->host_only && !p->batched && level >= 0 && size_t(level) < p->passes.size()) return MOA_ERR_STATE;
     if (p->batched) {
@@ -994,8 +1179,15 @@ moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t lev
     if (p->host_only) return MOA_ERR_STATE;
     if (!pair_aligned(p->passes[size_t(level)], in, out, true, true)) return MOA_ERR_ARG;
     std::vector<moa::PassArgs> args;
-    pass_args(p, int(dir), in, out, args);
-    return moa::launch_pass(p->fp64, p->passes[size_t(level)], args[size_t(level)],
+    pass_args(p, int(dir), in, out, p->d_ws, args);
+    moa::PassArgs& a = args[size_t(level)];
+    // One level runs from `in` to `out` whatever its position (a lifted plan's
+    // middle levels otherwise read and write the workspace).
+    if (!p->dims.empty()) {
+        a.in = in;
+        a.out = out;
+    }
+    return moa::launch_pass(p->fp64, p->passes[size_t(level)], a,
                             static_cast<hipStream_t>(stream)) == hipSuccess
                ? MOA_OK
                : MOA_ERR_HIP;
@@ -1003,7 +1195,8 @@ moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t lev
 
 moa_status_t moa_fft_num_levels(moa_fft_plan_t p, int32_t* levels)
 {
-    if (!valid_plan(p) || !levels) return MOA_ERR_NULL;
+    if (const moa_status_t hs = check_plan(p)) return hs;
+    if (!levels) return MOA_ERR_NULL;
     if (p->batched)
         *levels = (p->flags & MOA_FFT_FLAG_PER_SIZE) ? int32_t(p->size_ranges.size()) : 1;
     else
@@ -1013,21 +1206,24 @@ moa_status_t moa_fft_num_levels(moa_fft_plan_t p, int32_t* levels)
 
 moa_status_t moa_fft_workspace_size(moa_fft_plan_t p, size_t* bytes)
 {
-    if (!valid_plan(p) || !bytes) return MOA_ERR_NULL;
+    if (const moa_status_t hs = check_plan(p)) return hs;
+    if (!bytes) return MOA_ERR_NULL;
     *bytes = p->ws_bytes;
     return MOA_OK;
 }
 
 moa_status_t moa_fft_describe_size(moa_fft_plan_t p, size_t* bytes)
 {
-    if (!valid_plan(p) || !bytes) return MOA_ERR_NULL;
+    if (const moa_status_t hs = check_plan(p)) return hs;
+    if (!bytes) return MOA_ERR_NULL;
     *bytes = describe_json(p).size() + 1;
     return MOA_OK;
 }
 
 moa_status_t moa_fft_describe(moa_fft_plan_t p, char* buf, size_t len)
 {
-    if (!valid_plan(p) || !buf) return MOA_ERR_NULL;
+    if (const moa_status_t hs = check_plan(p)) return hs;
+    if (!buf) return MOA_ERR_NULL;
     const std::string s = describe_json(p);
     if (len == 0) return MOA_ERR_ARG;
     const size_t k = std::min(len - 1, s.size());
@@ -1039,7 +1235,10 @@ moa_status_t moa_fft_describe(moa_fft_plan_t p, char* buf, size_t len)
 moa_status_t moa_fft_destroy(moa_fft_plan_t p)
 {
     if (!p) return MOA_OK;
-    if (!valid_plan(p)) return MOA_ERR_STATE;
+    {
+        std::lock_guard<std::mutex> lock(registry_mutex());
+        if (registry().erase(p) == 0) return MOA_ERR_STATE;
+    }
     release(p);
     p->magic = 0;
     delete p;

@@ -7,6 +7,7 @@ there is no CPU or library fallback.
 
 * :class:`Plan` -- ``batch`` contiguous transforms of length n with a lift.
 * :class:`BatchedPlan` -- an uneven batch of power-of-two lengths, packed.
+* :class:`NDPlan` -- ``batch`` contiguous multi-dimensional transforms.
 * :func:`fft` / :func:`adjoint` -- cached-plan convenience calls on the last
   axis (unnormalised; ``adjoint(fft(x)) == n * x``).
 * :class:`FFTFunction` -- autograd: backward of the forward transform is the
@@ -153,6 +154,34 @@ class BatchedPlan(_PlanBase):
             self._h = capi.moa_fft_plan_batched(self.sizes, _dtype_code(dtype), flags, tuning)
 
 
+class NDPlan(_PlanBase):
+    """``batch`` contiguous multi-dimensional transforms of shape ``dims``
+    (row-major, the last axis contiguous): one launch per axis of extent
+    > 1, in -> out first, then in place in out."""
+
+    def __init__(self, dims: Sequence[int], batch: int = 1, dtype: torch.dtype = torch.complex64,
+                 prec: str = "native", graph: bool = False, tuning: Optional[dict] = None,
+                 device: Optional[torch.device] = None, host_only: bool = False):
+        super().__init__()
+        if prec not in _PREC:
+            raise ValueError(f"prec must be one of {sorted(_PREC)}")
+        self.dims = [int(d) for d in dims]
+        self.batch, self.dtype, self.prec = int(batch), dtype, prec
+        n = 1
+        for d in self.dims:
+            n *= d
+        self.n = n
+        self.numel = n * self.batch
+        if host_only:
+            self.device = torch.device("cpu")
+        else:
+            self.device = torch.device(device) if device is not None else torch.device(
+                "cuda", torch.cuda.current_device())
+        flags = (capi.MOA_FFT_FLAG_GRAPH if graph else 0) | (capi.MOA_FFT_FLAG_HOST_ONLY if host_only else 0)
+        with torch.cuda.device(self.device) if not host_only else _nullctx():
+            self._h = capi.moa_fft_plan_nd(self.dims, self.batch, _dtype_code(dtype), _PREC[prec], flags, tuning)
+
+
 class _nullctx:
     def __enter__(self):
         return None
@@ -161,20 +190,36 @@ class _nullctx:
         return False
 
 
+# Plans of the convenience calls, one per (shape, dtype, precision, device,
+# stream): a multi-level plan's workspace is shared by its executions, which
+# the library requires to be serialised on one stream, so calls from
+# different streams get different plans.  An evicted plan is only dropped
+# from the cache (its memory goes when the last reference does); a plan used
+# while its stream is being captured into a graph is kept for the life of
+# the process, since the graph keeps its workspace and tables.
 _cache: dict = {}
+_pinned: list = []
 _cache_lock = threading.Lock()
 
 
-def _cached_plan(n: int, batch: int, lift, dtype, prec, device) -> Plan:
-    key = (n, batch, tuple(lift) if lift else None, dtype, prec, device)
+def _cached(key, make):
+    stream = torch.cuda.current_stream(key[-1])
+    key = key + (stream.cuda_stream,)
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
             if len(_cache) >= 32:
-                _cache.pop(next(iter(_cache))).close()
-            p = Plan(n, batch, lift, dtype, prec, device=device)
+                _cache.pop(next(iter(_cache)))
+            p = make()
             _cache[key] = p
+        if torch.cuda.is_current_stream_capturing() and not any(q is p for q in _pinned):
+            _pinned.append(p)
         return p
+
+
+def _cached_plan(n: int, batch: int, lift, dtype, prec, device) -> Plan:
+    return _cached(("1d", n, batch, tuple(lift) if lift else None, dtype, prec, device),
+                   lambda: Plan(n, batch, lift, dtype, prec, device=device))
 
 
 def _apply(x: torch.Tensor, direction: int, lift, prec) -> torch.Tensor:
@@ -185,6 +230,30 @@ def _apply(x: torch.Tensor, direction: int, lift, prec) -> torch.Tensor:
     batch = xc.numel() // n if n else 0
     p = _cached_plan(n, batch, lift, xc.dtype, prec, xc.device)
     return p._exec(direction, xc, None)
+
+
+def _apply_nd(x: torch.Tensor, direction: int, ndim: int, prec) -> torch.Tensor:
+    if ndim < 1 or ndim > x.dim():
+        raise ValueError("ndim must be between 1 and x.dim()")
+    dims = [int(d) for d in x.shape[x.dim() - ndim:]]
+    xc = x.contiguous()
+    n = 1
+    for d in dims:
+        n *= d
+    batch = xc.numel() // n if n else 0
+    p = _cached(("nd", tuple(dims), batch, xc.dtype, prec, xc.device),
+                lambda: NDPlan(dims, batch, xc.dtype, prec, device=xc.device))
+    return p._exec(direction, xc, None)
+
+
+def fftn(x: torch.Tensor, ndim: int, prec: str = "native") -> torch.Tensor:
+    """Forward transform over the last ``ndim`` axes (unnormalised)."""
+    return _apply_nd(x, capi.MOA_FFT_FORWARD, ndim, prec)
+
+
+def adjointn(y: torch.Tensor, ndim: int, prec: str = "native") -> torch.Tensor:
+    """Adjoint (conjugate, unnormalised) transform over the last ``ndim`` axes."""
+    return _apply_nd(y, capi.MOA_FFT_ADJOINT, ndim, prec)
 
 
 def fft(x: torch.Tensor, lift: Optional[Sequence[int]] = None, prec: str = "native") -> torch.Tensor:
@@ -213,3 +282,17 @@ class FFTFunction(torch.autograd.Function):
 
 def fft_autograd(x: torch.Tensor, lift=None, prec: str = "native") -> torch.Tensor:
     return FFTFunction.apply(x, lift, prec)
+
+
+class FFTNFunction(torch.autograd.Function):
+    """y = F x over the last ``ndim`` axes; backward is the adjoint transform
+    of the incoming gradient over the same axes."""
+
+    @staticmethod
+    def forward(ctx, x, ndim, prec="native"):
+        ctx.ndim, ctx.prec = ndim, prec
+        return fftn(x, ndim, prec)
+
+    @staticmethod
+    def backward(ctx, g):
+        return adjointn(g.contiguous(), ctx.ndim, ctx.prec), None, None

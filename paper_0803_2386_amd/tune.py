@@ -7,7 +7,8 @@ experiment, not from the cache size).  Here the candidates are lifts whose
 levels each fit one workgroup, in the paper's uniform form
 <2^p_max c ... c> and in balanced mixed forms, each with a few tile widths;
 every candidate is planned through the C ABI, timed with HIP events, and the
-fastest is cached in a JSON file keyed by device, dtype, n and batch
+fastest is cached in a JSON file keyed by device, dtype, precision, n, batch,
+the search limits and a digest of the built library
 (``$MOA_FFT_TUNE_CACHE``, default ``~/.cache/moa_fft_tune.json``).  Timing is
 the only thing done here; all arithmetic runs in the library's kernels.
 """
@@ -46,8 +47,30 @@ def _save_cache(c: dict) -> None:
     os.replace(tmp, path)
 
 
-def _key(device_name: str, dtype_code: int, n: int, batch: int, prec: int) -> str:
-    return f"{device_name}|{'c64' if dtype_code == capi.MOA_C64 else 'c128'}|p{prec}|n{n}|b{batch}"
+_lib_digest = None
+
+
+def library_digest() -> str:
+    """Short sha256 of the built library: a rebuilt kernel set invalidates
+    the cached picks of the old one."""
+    global _lib_digest
+    if _lib_digest is None:
+        import hashlib
+        h = hashlib.sha256()
+        with open(capi.LIB_PATH, "rb") as f:
+            for chunk in iter(lambda: f.read(1 << 20), b""):
+                h.update(chunk)
+        _lib_digest = h.hexdigest()[:16]
+    return _lib_digest
+
+
+def _key(device_name: str, dtype_code: int, n: int, batch: int, prec: int, max_levels: int = 3,
+         limit: Optional[int] = None, refine: int = 5) -> str:
+    """Cache key: the problem, the search that answered it (a search cut
+    short by a candidate limit is not the answer of a full one) and the
+    library it timed."""
+    return (f"{device_name}|{'c64' if dtype_code == capi.MOA_C64 else 'c128'}|p{prec}|n{n}|b{batch}"
+            f"|L{max_levels}|lim{limit or 0}|r{refine}|lib{library_digest()}")
 
 
 def lift_candidates(n: int, dtype_code: int = capi.MOA_C64, max_levels: int = 3) -> List[List[int]]:
@@ -136,7 +159,7 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
     pcode = mfft._PREC[prec]
     dev = torch.device("cuda", torch.cuda.current_device())
     name = torch.cuda.get_device_name(dev)
-    key = _key(name, dcode, n, batch, pcode)
+    key = _key(name, dcode, n, batch, pcode, max_levels, candidates_limit, refine)
     if use_cache:
         with _lock:
             hit = _load_cache().get(key)

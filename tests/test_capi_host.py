@@ -369,3 +369,92 @@ def test_pair_block_workspace_computes_the_dft():
     want = oracle.fft(x)
     assert np.abs(got - want).max() < 1e-9 * np.abs(want).max()
 
+
+
+def describe_nd(dims, batch=1, dtype=capi.MOA_C64, prec=capi.MOA_FFT_PREC_NATIVE, tuning=None):
+    h = capi.moa_fft_plan_nd(dims, batch, dtype=dtype, prec=prec, flags=HOST, tuning=tuning)
+    try:
+        return json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+
+
+@pytest.mark.parametrize("dims,batch,kw,want", [
+    ([3, 4], 1, {}, capi.MOA_ERR_SIZE), ([0, 4], 1, {}, capi.MOA_ERR_SIZE), ([1 << 15, 2], 1, {}, capi.MOA_ERR_SIZE),
+    ([1 << 14, 2], 1, dict(dtype=capi.MOA_C128), capi.MOA_ERR_SIZE),
+    ([1 << 14, 1 << 14, 8], 1, {}, capi.MOA_ERR_SIZE),        # 2^31 points
+    ([], 1, {}, capi.MOA_ERR_ARG), ([2] * 9, 1, {}, capi.MOA_ERR_ARG),
+    ([16, 16], 0, {}, capi.MOA_ERR_BATCH), ([16, 16], 1, dict(dtype=9), capi.MOA_ERR_DTYPE),
+    ([16, 16], 1, dict(flags=capi.MOA_FFT_FLAG_PER_SIZE), capi.MOA_ERR_ARG),
+    ([64, 64], 1, dict(tuning=dict(cols_per_block=[3])), capi.MOA_ERR_TUNING),
+    ([4096, 4096], 1, {}, capi.MOA_OK), ([256, 256, 256], 1, {}, capi.MOA_OK), ([1, 1], 3, {}, capi.MOA_OK),
+    ([1 << 14, 1 << 14, 4], 1, {}, capi.MOA_OK), ([2] * 8, 5, {}, capi.MOA_OK),
+])
+def test_nd_plan_validation(dims, batch, kw, want):
+    kw = dict(kw)
+    kw["flags"] = kw.get("flags", 0) | HOST
+    if not dims:
+        lib = capi.load()
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_int64 * 1)(4)
+        assert lib.moa_fft_plan_nd(ctypes.byref(h), 0, arr, 1, 0, 0, HOST) == want
+        return
+    assert status_of(capi.moa_fft_plan_nd, dims, batch, **kw) == want
+
+
+def test_nd_null_pointers():
+    lib = capi.load()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * 2)(4, 4)
+    assert lib.moa_fft_plan_nd(None, 2, arr, 1, 0, 0, HOST) == capi.MOA_ERR_NULL
+    assert lib.moa_fft_plan_nd(ctypes.byref(h), 2, None, 1, 0, 0, HOST) == capi.MOA_ERR_NULL
+
+
+@pytest.mark.parametrize("dims,batch", [
+    ((8, 16), 1), ((16, 8), 3), ((4, 8, 2), 2), ((1, 64), 1), ((32, 1, 4), 1), ((2, 2, 2, 2), 2), ((1, 1), 2),
+    ((64, 64), 1), ((4096, 2), 1), ((2, 4096), 1), ((16, 256), 2), ((16, 16, 16), 1),
+])
+def test_nd_lowering_computes_the_dft(dims, batch):
+    desc = describe_nd(list(dims), batch)
+    assert desc["kind"] == "nd" and desc["dims"] == list(dims) and desc["workspace_bytes"] == 0
+    ext = [d for d in dims if d > 1]
+    assert len(desc["passes"]) == max(1, len(ext))
+    for p in desc["passes"]:
+        assert p["twiddle_root"] == 0 and p["out"] == "y"
+    rng = np.random.default_rng(sum(dims) + batch)
+    N = int(np.prod(dims))
+    x = rng.uniform(-1, 1, N * batch) + 1j * rng.uniform(-1, 1, N * batch)
+    for sign in (-1, 1):
+        got = interpret_fast(desc, x, sign).reshape((batch,) + tuple(dims))
+        want = oracle.fftn(x.reshape((batch,) + tuple(dims)), len(dims), sign)
+        assert np.abs(got - want).max() < 1e-11 * N, (dims, batch, sign)
+
+
+def test_nd_headline_shapes_pick_the_wide_tile_kernels():
+    d = describe_nd([4096, 4096])
+    # contiguous rows first (one 4096-point row a tile), then the columns in
+    # the paired-column kernel (unit-stride tile digit on both sides)
+    assert [p["dft_axis"]["in_stride"] for p in d["passes"]] == [1, 4096]
+    assert d["passes"][1]["kernel_mode"] == 3 and d["passes"][1]["in_tile_fast"] and d["passes"][1]["out_tile_fast"]
+    d3 = describe_nd([256, 256, 256])
+    assert [p["dft_axis"]["in_stride"] for p in d3["passes"]] == [1, 256, 65536]
+    for p in d3["passes"][1:]:
+        assert p["in_tile_fast"] and p["tile_width"] * 8 >= 128   # whole 128-byte lines per row
+
+
+def test_stale_and_double_destroyed_handles_are_rejected():
+    lib = capi.load()
+    h = capi.moa_fft_plan(1024, 1, None, flags=HOST)
+    assert lib.moa_fft_destroy(h) == capi.MOA_OK
+    # the handle is gone: every call reports it without touching memory
+    assert lib.moa_fft_destroy(h) == capi.MOA_ERR_STATE
+    size = ctypes.c_size_t()
+    lv = ctypes.c_int32()
+    assert lib.moa_fft_workspace_size(h, ctypes.byref(size)) == capi.MOA_ERR_STATE
+    assert lib.moa_fft_num_levels(h, ctypes.byref(lv)) == capi.MOA_ERR_STATE
+    assert lib.moa_fft_exec(h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == capi.MOA_ERR_STATE
+    assert lib.moa_fft_describe_size(h, ctypes.byref(size)) == capi.MOA_ERR_STATE
+    # a pointer that never was a plan
+    junk = ctypes.create_string_buffer(256)
+    assert lib.moa_fft_destroy(ctypes.cast(junk, ctypes.c_void_p)) == capi.MOA_ERR_STATE
+    assert lib.moa_fft_num_levels(ctypes.cast(junk, ctypes.c_void_p), ctypes.byref(lv)) == capi.MOA_ERR_STATE

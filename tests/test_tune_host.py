@@ -28,3 +28,11 @@ def test_candidates_plan_on_host():
     assert len(cands) > 5
     lifts = {tuple(l) for l, _ in cands}
     assert (256, 256) in lifts and (1 << 16,) not in lifts
+
+
+def test_cache_key_names_the_search_and_the_library():
+    k_full = tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 3, None, 5)
+    k_cut = tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 3, 12, 5)
+    k_deep = tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 4, None, 5)
+    assert len({k_full, k_cut, k_deep}) == 3
+    assert tune.library_digest() in k_full
