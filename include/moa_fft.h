@@ -72,7 +72,9 @@ typedef enum {
     MOA_ERR_HIP = 7,         /* a HIP runtime call failed                      */
     MOA_ERR_STATE = 8,       /* plan is host-only (cannot execute) or invalid  */
     MOA_ERR_ARG = 9,         /* other invalid argument (direction, flags, len) */
-    MOA_ERR_TUNING = 10      /* tuning parameters outside the kernel's limits  */
+    MOA_ERR_TUNING = 10,     /* tuning parameters outside the kernel's limits  */
+    MOA_ERR_SCRATCH = 11     /* moa_fft_exec_noalloc: the plan needs more
+                                workspace than MOA_FFT_SCRATCH_BYTES          */
 } moa_status_t;
 
 /* Flags for the plan constructors. */
@@ -86,6 +88,16 @@ typedef enum {
                                          (direction, in, out) once as a HIP
                                          graph of kernel nodes and replay it
                                          with one hipGraphLaunch per exec   */
+#define MOA_FFT_FLAG_NO_WORKSPACE 0x8u /* allocate no workspace: a plan with
+                                         more than one level then runs only
+                                         through moa_fft_exec_noalloc
+                                         (moa_fft_exec and moa_fft_exec_level
+                                         return MOA_ERR_STATE)               */
+
+/* Bytes of the library's static device workspace used by
+ * moa_fft_exec_noalloc on each GPU: 64 MiB, the workspace of 2^23 complex64
+ * or 2^22 complex128 points. */
+#define MOA_FFT_SCRATCH_BYTES ((size_t)64 << 20)
 
 /* Optional launch tuning, one entry per level of the lift (level 0 = the
  * innermost block c, the first pass).  Zero entries select the defaults. */
@@ -204,6 +216,33 @@ moa_status_t moa_fft_plan_batched_tuned(moa_fft_plan_t* out, const int64_t* size
  */
 moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out,
                           void* stream);
+
+/*
+ * moa_fft_exec for callers that cannot allocate device memory: code under
+ * HIP graph (stream) capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It calls no hipMalloc, hipFree or allocating library routine
+ * and builds no HIP graph (a MOA_FFT_FLAG_GRAPH plan's launches are issued
+ * directly).  The workspace a plan of several levels needs (batch * n
+ * complex elements) is taken from a static device array of
+ * MOA_FFT_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * the process ends, instead of the plan's own workspace, so the plan may be
+ * made with MOA_FFT_FLAG_NO_WORKSPACE.  Plans of one level (and uneven
+ * batches) need none and run exactly as with moa_fft_exec.
+ *
+ * Every call on one GPU shares that GPU's array: calls whose executions
+ * overlap on one GPU (two streams, or two host threads) race and give wrong
+ * results; serialise them on one stream.  The array keeps the last call's
+ * contents; nothing in it needs to start at zero (the first level of an
+ * execution writes all of the workspace before any level reads it).
+ *
+ * Arguments and result as moa_fft_exec (the buffers stay the caller's).
+ * Errors: those of moa_fft_exec, plus MOA_ERR_SCRATCH when the plan needs
+ * more than MOA_FFT_SCRATCH_BYTES of workspace (checked on the host before
+ * any HIP call), and MOA_ERR_HIP if the array's device address cannot be
+ * obtained.
+ */
+moa_status_t moa_fft_exec_noalloc(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out,
+                                  void* stream);
 
 /*
  * Run only level `level` of a lifted plan (one kernel launch): level 0 reads

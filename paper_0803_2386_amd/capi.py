@@ -32,15 +32,19 @@ MOA_ERR_HIP = 7
 MOA_ERR_STATE = 8
 MOA_ERR_ARG = 9
 MOA_ERR_TUNING = 10
+MOA_ERR_SCRATCH = 11
 
 MOA_FFT_FLAG_HOST_ONLY = 0x1
 MOA_FFT_FLAG_PER_SIZE = 0x2
 MOA_FFT_FLAG_GRAPH = 0x4
+MOA_FFT_FLAG_NO_WORKSPACE = 0x8
+
+MOA_FFT_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = [
     "moa_fft_plan", "moa_fft_plan_tuned", "moa_fft_plan_nd", "moa_fft_plan_nd_tuned",
     "moa_fft_plan_batched", "moa_fft_plan_batched_tuned",
-    "moa_fft_exec", "moa_fft_exec_level", "moa_fft_num_levels", "moa_fft_workspace_size", "moa_fft_describe", "moa_fft_describe_size",
+    "moa_fft_exec", "moa_fft_exec_noalloc", "moa_fft_exec_level", "moa_fft_num_levels", "moa_fft_workspace_size", "moa_fft_describe", "moa_fft_describe_size",
     "moa_fft_destroy", "moa_fft_status_string", "moa_fft_max_block",
 ]
 
@@ -87,6 +91,7 @@ def load() -> ctypes.CDLL:
         "moa_fft_plan_batched": ([PP, I64P, I64, E, U32], E),
         "moa_fft_plan_batched_tuned": ([PP, I64P, I64, E, U32, TP], E),
         "moa_fft_exec": ([P, E, P, P, P], E),
+        "moa_fft_exec_noalloc": ([P, E, P, P, P], E),
         "moa_fft_exec_level": ([P, E, I32, P, P, P], E),
         "moa_fft_num_levels": ([P, ctypes.POINTER(I32)], E),
         "moa_fft_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], E),
@@ -181,6 +186,13 @@ def moa_fft_exec(plan, direction, in_ptr: int, out_ptr: int, stream: int = 0) ->
                              ctypes.c_void_p(stream))
     if st != MOA_OK:
         raise MoaError(st, "moa_fft_exec")
+
+
+def moa_fft_exec_noalloc(plan, direction, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    st = load().moa_fft_exec_noalloc(plan, int(direction), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                     ctypes.c_void_p(stream))
+    if st != MOA_OK:
+        raise MoaError(st, "moa_fft_exec_noalloc")
 
 
 def moa_fft_exec_level(plan, direction, level: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:

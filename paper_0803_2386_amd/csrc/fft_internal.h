@@ -3,11 +3,15 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "../../include/moa_fft.h"
 
 namespace moa {
 
 constexpr int kMaxDigits = 8;     // batch digits of one pass descriptor
+constexpr int kMaxPasses = 8;     // passes of one plan (lift rank or array rank <= 8)
 constexpr int kMaxThreads = 512;  // level-kernel workgroup limit (1024: staged-store, paired-column and batch kernels)
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kNoBlock = 30;      // lgb of an axis with one plain stride
@@ -176,6 +180,13 @@ const void* pair_kernel_fn(const PassDesc& d, bool fwd);
 hipError_t launch_small(bool fp64, const PassDesc& d, const PassArgs& a, hipStream_t s);
 hipError_t prepare_small_kernel(bool fp64, const PassDesc& d);
 const void* small_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
+// Execution on a workspace the caller of these two supplies (the
+// allocation-free entry point in scratch.hip).  check_exec validates like
+// moa_fft_exec, host-side only, and reports the workspace bytes the plan's
+// launches need; launch_on_workspace then launches them directly (never
+// through the plan's graphs) with `ws` as the workspace.
+moa_status_t check_exec(moa_fft_plan_t p, int dir, const void* in, const void* out, size_t* ws_bytes);
+moa_status_t launch_on_workspace(moa_fft_plan_t p, int dir, const void* in, void* out, void* ws, hipStream_t s);
 // The kernel function pointers, used to build HIP graph nodes.
 const void* pass_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
 const void* batched_kernel_fn(bool fp64, bool fwd);

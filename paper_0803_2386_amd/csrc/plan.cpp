@@ -27,7 +27,8 @@ namespace {
 
 constexpr uint32_t kMagic = 0x4d4f4146u;  // "MOAF"
 constexpr int kLgMaxN = 30;
-constexpr uint32_t kKnownFlags = MOA_FFT_FLAG_HOST_ONLY | MOA_FFT_FLAG_PER_SIZE | MOA_FFT_FLAG_GRAPH;
+constexpr uint32_t kKnownFlags =
+    MOA_FFT_FLAG_HOST_ONLY | MOA_FFT_FLAG_PER_SIZE | MOA_FFT_FLAG_GRAPH | MOA_FFT_FLAG_NO_WORKSPACE;
 
 bool is_pow2(int64_t x) { return x >= 1 && (x & (x - 1)) == 0; }
 int lg2(int64_t x)
@@ -498,7 +499,7 @@ moa_status_t upload(moa_fft_plan_s* p)
     }
     if (hipMalloc(&p->d_tables, buf.size()) != hipSuccess) return MOA_ERR_ALLOC;
     if (hipMemcpy(p->d_tables, buf.data(), buf.size(), hipMemcpyHostToDevice) != hipSuccess) return MOA_ERR_HIP;
-    if (p->ws_bytes) {
+    if (p->ws_bytes && !(p->flags & MOA_FFT_FLAG_NO_WORKSPACE)) {
         if (hipMalloc(&p->d_ws, p->ws_bytes) != hipSuccess) return MOA_ERR_ALLOC;
     }
     if (!p->tasks.empty()) {
@@ -606,8 +607,9 @@ std::string describe_json(const moa_fft_plan_s* p)
         p->batched ? "uneven_batch" : (p->dims.empty() ? "lifted" : "nd"), p->fp64 ? "c128" : "c64",
         p->prec == MOA_FFT_PREC_NATIVE ? "native" : (p->prec == MOA_FFT_PREC_SPLIT_BF16 ? "split_bf16" : "split_fp16"),
         (long long)p->n, (long long)p->batch, (long long)p->total);
-    add("\"host_only\":%s,\"workspace_bytes\":%zu,\"stream\":%s,", p->host_only ? "true" : "false",
-        p->ws_bytes, p->stream ? "true" : "false");
+    add("\"host_only\":%s,\"workspace_bytes\":%zu,\"workspace_owned\":%s,\"stream\":%s,",
+        p->host_only ? "true" : "false", p->ws_bytes,
+        (p->ws_bytes && !(p->flags & MOA_FFT_FLAG_NO_WORKSPACE)) ? "true" : "false", p->stream ? "true" : "false");
     s += "\"lift\":[";
     for (size_t i = 0; i < p->lift.size(); ++i) add("%s%lld", i ? "," : "", (long long)p->lift[i]);
     if (!p->dims.empty()) {
@@ -687,12 +689,11 @@ moa_status_t stream_choice(const moa_fft_tuning_t* tuning, size_t in_bytes, bool
 // middle levels in place in the workspace `ws` and writes `out` on its last
 // level; a multi-dimensional plan transforms one axis a pass, `in` -> `out`
 // first, then in place in `out`.
-void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, void* ws,
-               std::vector<moa::PassArgs>& args)
+// Fills args[0 .. passes) (a fixed array: an execution allocates nothing).
+void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, void* ws, moa::PassArgs* args)
 {
     const size_t eb = elem_bytes(p->fp64);
     const unsigned char* tb = static_cast<const unsigned char*>(p->d_tables);
-    args.clear();
     const size_t P = p->passes.size();
     const bool nd = !p->dims.empty();
     for (size_t l = 0; l < P; ++l) {
@@ -742,7 +743,7 @@ void pass_args(const moa_fft_plan_s* p, int dir, const void* in, void* out, void
         a.out_pair_s = d.out_pair_s ? d.out_pair_s : 2 * d.out_s[0];
         a.in_tile_s = d.in_tile_s ? d.in_tile_s : (int64_t(1) << d.lgw) * d.in_s[0];
         a.out_tile_s = d.out_tile_s ? d.out_tile_s : (int64_t(1) << d.lgw) * d.out_s[0];
-        args.push_back(a);
+        args[l] = a;
     }
 }
 
@@ -779,7 +780,7 @@ moa_status_t launch_all(moa_fft_plan_s* p, int dir, const void* in, void* out, v
         }
         return MOA_OK;
     }
-    std::vector<moa::PassArgs> args;
+    moa::PassArgs args[moa::kMaxPasses];
     pass_args(p, dir, in, out, ws, args);
     for (size_t l = 0; l < p->passes.size(); ++l)
         if (moa::launch_pass(p->fp64, p->passes[l], args[l], s) != hipSuccess) return MOA_ERR_HIP;
@@ -827,7 +828,7 @@ moa_status_t make_graph(moa_fft_plan_s* p, int dir, const void* in, void* out, G
                           dim3(unsigned(p->batch_threads)), p->batch_lds, &a);
         }
     } else {
-        std::vector<moa::PassArgs> args;
+        moa::PassArgs args[moa::kMaxPasses];
         pass_args(p, dir, in, out, p->d_ws, args);
         for (size_t l = 0; l < p->passes.size() && st == MOA_OK; ++l) {
             const PassDesc& d = p->passes[l];
@@ -912,7 +913,51 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     return MOA_OK;
 }
 
+// Paired-column levels move column pairs with 16-byte accesses on their
+// unit-stride side; a caller buffer on that side must be 16-byte aligned.
+bool pair_aligned(const PassDesc& d, const void* in, const void* out, bool reads_in, bool writes_out)
+{
+    if (d.kmode != 3) return true;
+    if (reads_in && d.in_tile_fast && (reinterpret_cast<uintptr_t>(in) & 15u)) return false;
+    if (writes_out && d.out_tile_fast && (reinterpret_cast<uintptr_t>(out) & 15u)) return false;
+    return true;
+}
+
+// Every pass's caller buffers meet the paired-column alignment: a 1-D plan
+// reads `in` on level 0 and writes `out` on its last level; a
+// multi-dimensional plan reads `in` on its first pass and `out` after it,
+// and writes `out` on every pass.
+bool exec_aligned(const moa_fft_plan_s* p, const void* in, const void* out)
+{
+    const size_t P = p->passes.size();
+    for (size_t l = 0; l < P; ++l) {
+        const bool ok = p->dims.empty() ? pair_aligned(p->passes[l], in, out, l == 0, l + 1 == P)
+                                        : pair_aligned(p->passes[l], l == 0 ? in : out, out, true, true);
+        if (!ok) return false;
+    }
+    return true;
+}
+
 }  // namespace
+
+// Execution on a workspace supplied by the caller of these two functions
+// (the allocation-free entry point keeps it in a static device array).
+moa_status_t moa::check_exec(moa_fft_plan_t p, int dir, const void* in, const void* out, size_t* ws_bytes)
+{
+    if (const moa_status_t hs = check_plan(p)) return hs;
+    if (!in || !out || !ws_bytes) return MOA_ERR_NULL;
+    if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
+    *ws_bytes = p->ws_bytes;
+    if (p->ws_bytes > MOA_FFT_SCRATCH_BYTES) return MOA_ERR_SCRATCH;
+    if (p->host_only) return MOA_ERR_STATE;
+    if (!exec_aligned(p, in, out)) return MOA_ERR_ARG;
+    return MOA_OK;
+}
+
+moa_status_t moa::launch_on_workspace(moa_fft_plan_t p, int dir, const void* in, void* out, void* ws, hipStream_t s)
+{
+    return launch_all(p, dir, in, out, ws, s);
+}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -933,6 +978,7 @@ const char* moa_fft_status_string(moa_status_t s)
         case MOA_ERR_STATE: return "MOA_ERR_STATE";
         case MOA_ERR_ARG: return "MOA_ERR_ARG";
         case MOA_ERR_TUNING: return "MOA_ERR_TUNING";
+        case MOA_ERR_SCRATCH: return "MOA_ERR_SCRATCH";
     }
     return "MOA_ERR_UNKNOWN";
 }
@@ -1099,37 +1145,13 @@ moa_status_t moa_fft_plan_batched(moa_fft_plan_t* out, const int64_t* sizes, int
     return moa_fft_plan_batched_tuned(out, sizes, count, dtype, flags, nullptr);
 }
 
-// Paired-column levels move column pairs with 16-byte accesses on their
-// unit-stride side; a caller buffer on that side must be 16-byte aligned.
-static bool pair_aligned(const PassDesc& d, const void* in, const void* out, bool reads_in, bool writes_out)
-{
-    if (d.kmode != 3) return true;
-    if (reads_in && d.in_tile_fast && (reinterpret_cast<uintptr_t>(in) & 15u)) return false;
-    if (writes_out && d.out_tile_fast && (reinterpret_cast<uintptr_t>(out) & 15u)) return false;
-    return true;
-}
-
-// Every pass's caller buffers meet the paired-column alignment: a 1-D plan
-// reads `in` on level 0 and writes `out` on its last level; a
-// multi-dimensional plan reads `in` on its first pass and `out` after it,
-// and writes `out` on every pass.
-static bool exec_aligned(const moa_fft_plan_s* p, const void* in, const void* out)
-{
-    const size_t P = p->passes.size();
-    for (size_t l = 0; l < P; ++l) {
-        const bool ok = p->dims.empty() ? pair_aligned(p->passes[l], in, out, l == 0, l + 1 == P)
-                                        : pair_aligned(p->passes[l], l == 0 ? in : out, out, true, true);
-        if (!ok) return false;
-    }
-    return true;
-}
-
 moa_status_t moa_fft_exec(moa_fft_plan_t p, moa_fft_dir_t dir, const void* in, void* out, void* stream)
 {
     if (const moa_status_t hs = check_plan(p)) return hs;
     if (!in || !out) return MOA_ERR_NULL;
     if (dir != MOA_FFT_FORWARD && dir != MOA_FFT_ADJOINT) return MOA_ERR_ARG;
     if (p->host_only) return MOA_ERR_STATE;
+    if (p->ws_bytes && !p->d_ws) return MOA_ERR_STATE;  // planned without a workspace
     if (!exec_aligned(p, in, out)) return MOA_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!(p->flags & MOA_FFT_FLAG_GRAPH)) return launch_all(p, int(dir), in, out, p->d_ws, s);
@@ -1177,8 +1199,9 @@ moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t lev
     }
     if (level < 0 || size_t(level) >= p->passes.size()) return MOA_ERR_ARG;
     if (p->host_only) return MOA_ERR_STATE;
+    if (p->ws_bytes && !p->d_ws) return MOA_ERR_STATE;  // planned without a workspace
     if (!pair_aligned(p->passes[size_t(level)], in, out, true, true)) return MOA_ERR_ARG;
-    std::vector<moa::PassArgs> args;
+    moa::PassArgs args[moa::kMaxPasses];
     pass_args(p, int(dir), in, out, p->d_ws, args);
     moa::PassArgs& a = args[size_t(level)];
     // One level runs from `in` to `out` whatever its position (a lifted plan's

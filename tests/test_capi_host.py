@@ -46,7 +46,8 @@ def test_exports_every_declared_symbol():
 def test_status_strings():
     for code, name in [(0, "MOA_OK"), (1, "MOA_ERR_NULL"), (2, "MOA_ERR_SIZE"), (3, "MOA_ERR_LIFT"),
                        (4, "MOA_ERR_BATCH"), (5, "MOA_ERR_DTYPE"), (6, "MOA_ERR_ALLOC"), (7, "MOA_ERR_HIP"),
-                       (8, "MOA_ERR_STATE"), (9, "MOA_ERR_ARG"), (10, "MOA_ERR_TUNING")]:
+                       (8, "MOA_ERR_STATE"), (9, "MOA_ERR_ARG"), (10, "MOA_ERR_TUNING"),
+                       (11, "MOA_ERR_SCRATCH")]:
         assert capi.moa_fft_status_string(code) == name
     assert capi.moa_fft_status_string(99) == "MOA_ERR_UNKNOWN"
     assert capi.moa_fft_max_block(capi.MOA_C64) == 1 << 14
@@ -108,6 +109,37 @@ def test_host_only_plan_cannot_execute_and_describe_truncates():
         assert json.loads(capi.moa_fft_describe(h))["n"] == 1024
     finally:
         capi.moa_fft_destroy(h)
+
+
+def test_exec_noalloc_validation_on_the_host():
+    """The allocation-free execution validates on the host before any HIP
+    call: a plan needing more workspace than the static array is refused
+    with MOA_ERR_SCRATCH, a host-only plan within it with MOA_ERR_STATE."""
+    lib = capi.load()
+    fn = lib.moa_fft_exec_noalloc
+    buf = ctypes.c_void_p(256)
+    assert fn(None, 0, buf, buf, None) == capi.MOA_ERR_NULL
+    big = capi.moa_fft_plan(1 << 24, 1, [4096, 4096], flags=HOST | capi.MOA_FFT_FLAG_NO_WORKSPACE)
+    fits = capi.moa_fft_plan(1 << 23, 1, [2048, 4096], flags=HOST | capi.MOA_FFT_FLAG_NO_WORKSPACE)
+    fits128 = capi.moa_fft_plan(1 << 22, 1, [1024, 4096], dtype=capi.MOA_C128, flags=HOST)
+    over128 = capi.moa_fft_plan(1 << 21, 3, [512, 4096], dtype=capi.MOA_C128, flags=HOST)
+    try:
+        assert capi.moa_fft_workspace_size(big) == 128 << 20
+        assert fn(big, 0, buf, buf, None) == capi.MOA_ERR_SCRATCH
+        assert fn(over128, 1, buf, buf, None) == capi.MOA_ERR_SCRATCH
+        assert capi.moa_fft_workspace_size(fits) == capi.MOA_FFT_SCRATCH_BYTES
+        assert fn(fits, 0, buf, buf, None) == capi.MOA_ERR_STATE
+        assert fn(fits128, 1, buf, buf, None) == capi.MOA_ERR_STATE
+        assert fn(fits, 2, buf, buf, None) == capi.MOA_ERR_ARG
+        assert fn(fits, 0, None, buf, None) == capi.MOA_ERR_NULL
+        d = json.loads(capi.moa_fft_describe(fits))
+        assert d["workspace_bytes"] == 64 << 20 and d["workspace_owned"] is False
+        assert json.loads(capi.moa_fft_describe(fits128))["workspace_owned"] is True
+    finally:
+        for h in (big, fits, fits128, over128):
+            capi.moa_fft_destroy(h)
+    # a destroyed plan is not a live plan
+    assert fn(big, 0, buf, buf, None) == capi.MOA_ERR_STATE
 
 
 @pytest.mark.parametrize("sizes,want", [([3], capi.MOA_ERR_SIZE), ([64, 1 << 15], capi.MOA_ERR_SIZE),
