@@ -89,10 +89,10 @@ typedef enum {
                                          graph of kernel nodes and replay it
                                          with one hipGraphLaunch per exec   */
 #define MOA_FFT_FLAG_NO_WORKSPACE 0x8u /* allocate no workspace: a plan with
-                                         more than one level then runs only
-                                         through moa_fft_exec_noalloc
-                                         (moa_fft_exec and moa_fft_exec_level
-                                         return MOA_ERR_STATE)               */
+                                         more than one level then runs whole
+                                         only through moa_fft_exec_noalloc
+                                         (moa_fft_exec returns MOA_ERR_STATE;
+                                         moa_fft_exec_level needs none)      */
 
 /* Bytes of the library's static device workspace used by
  * moa_fft_exec_noalloc on each GPU: 64 MiB, the workspace of 2^23 complex64
@@ -245,16 +245,27 @@ moa_status_t moa_fft_exec_noalloc(moa_fft_plan_t p, moa_fft_dir_t dir, const voi
                                   void* stream);
 
 /*
- * Run only level `level` of a lifted plan (one kernel launch): level 0 reads
- * `in`, later levels read the plan's workspace; the last level writes
- * `out`, earlier ones the workspace.  For a multi-dimensional plan level l
- * is the l-th axis launch and runs from `in` to `out`.  Running levels 0..L-1 in order equals
- * moa_fft_exec.  For timing and inspecting one level of the lift
- * ("The General Algorithm": one level = one pass over memory).  For an
- * uneven batch planned with MOA_FFT_FLAG_PER_SIZE, level g runs the
- * transforms of the g-th distinct length (longest first) from `in` to `out`;
- * for the fused form level 0 is the whole launch.  Errors as
- * moa_fft_exec, plus MOA_ERR_ARG for a level outside 0..L-1.
+ * Run only level `level` of a plan (one kernel launch) from `in` to `out`,
+ * for timing and inspecting one level of the lift ("The General
+ * Algorithm": one level = one pass over memory).  Level l reads `in` in the
+ * layout level l - 1 writes and writes `out` in the layout level l + 1
+ * reads, so running levels 0..L-1 in order through caller buffers of batch
+ * * n elements (level 0 reading x, the last level writing the result) equals
+ * moa_fft_exec.  The intermediate layout is the plan's workspace layout
+ * (moa_fft_describe: the digit strides of each pass, and the blocked
+ * out_layout / in_layout of a paired-column lift): after level 0 of a
+ * two-level lift <r c> it holds the length-c DFTs of the r stride-r columns
+ * multiplied by the inter-level factor omega_n^(a k), column a, frequency k.
+ * in == out is accepted only where the level stores in its load pattern:
+ * every level of a multi-dimensional plan, a single-level plan, the middle
+ * levels of a lift of three or more levels, and level 0 of a lift whose
+ * workspace keeps the digit positions (not the blocked paired-column
+ * layout); otherwise MOA_ERR_ARG.  For a multi-dimensional plan level l is
+ * the l-th axis launch.  For an uneven batch planned with
+ * MOA_FFT_FLAG_PER_SIZE, level g runs the transforms of the g-th distinct
+ * length (longest first) from `in` to `out`; for the fused form level 0 is
+ * the whole launch.  Needs no workspace.  Errors as moa_fft_exec, plus
+ * MOA_ERR_ARG for a level outside 0..L-1.
  */
 moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t level, const void* in,
                                 void* out, void* stream);

@@ -29,6 +29,9 @@ constexpr int kLgSmallMaxPoints = 19;
 
 // Entries of the in-block twiddle table kept in LDS (two halves of 128).
 constexpr int kTwBlkEntries = 256;
+// LDS elements after the tables of a matrix-core level: 16 floats, the
+// per-wave maxima from which an fp16 tile takes its scale.
+constexpr int kMfmaScaleElems = 8;
 
 // LDS twiddle entries of the short-transform kernel: omega_N^e for e < N up
 // to 2^kLgSmallDirect points, else a copy of the in-block table.

@@ -13,9 +13,13 @@
 // and a low half-precision part (x = hi + lo); three products hi*hi + hi*lo +
 // lo*hi are accumulated in float32 (the lo*lo term is below the accumulated
 // rounding).  Twiddles, the inter-level factor and all other arithmetic stay
-// float32.  For fp16 the data are scaled by an exact power of two before the
-// split (the square root of the growth bound of the stages before it), so
-// that both parts stay in the normal fp16 range, and unscaled after.
+// float32.  For fp16 every tile is scaled on entry by an exact power of two
+// taken from its data, 2^-e with e the exponent of the largest |re| or |im|
+// of the tile, so that its values lie below 1 whatever the input's range,
+// and unscaled by 2^e on exit.  A radix-16 stage grows the largest value by
+// at most 16 (unit twiddles), so the input of stage s stays below 16^s
+// (256 at the third stage of a 4096-point level), inside fp16's range, and
+// values near the tile's largest keep their low part in the normal range.
 //
 // Operand layouts of the 16x16x32 MFMA (lane l, 0 <= l < 64):
 //   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + i], i < 8
@@ -49,6 +53,29 @@ template <> struct SplitT<2> {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
     }
 };
+
+// Largest value of m over the 64 lanes of the wave.
+__device__ __forceinline__ float wave_max(float m)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    return m;
+}
+
+// Exact powers of two down = 2^-e, up = 2^e with m < 2^e (m >= 0), so that
+// m * down lies in [1/2, 1); e is clamped to [-100, 100] (a zero tile).  m is
+// the same in every lane: it is taken as a scalar, so the two factors live in
+// scalar registers (the vector registers are the kernels' limit).
+__device__ __forceinline__ void tile_scale(float m, float& down, float& up)
+{
+    const uint32_t bits = uint32_t(__builtin_amdgcn_readfirstlane(int(__float_as_uint(m))));
+    int e = int((bits >> 23) & 0xffu) - 126;
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    down = __uint_as_float(uint32_t(127 - e) << 23);
+    up = __uint_as_float(uint32_t(127 + e) << 23);
+}
+
+__device__ __forceinline__ float abs_max(float2 v, float m) { return fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))); }
 
 // Entry (row, col) of the real 32 x 32 DFT matrix.
 __device__ __forceinline__ double dft32_entry(int row, int col, float sign)
@@ -115,7 +142,10 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
     }
     // Coalesced copy of the tile into LDS along whichever axis is unit-stride;
     // each thread moves PPT points (T = W N / PPT) and issues all its loads
-    // before the first LDS store.
+    // before the first LDS store.  fp16: the largest |component| of the tile
+    // goes through one slot per wave after the tables.
+    float* wmax = reinterpret_cast<float*>(tt + 256 * a.tw_parts);
+    float tmax = 0.f;
     {
         const V* __restrict__ src = reinterpret_cast<const V*>(a.in) + ib;
         const bool tf = a.in_s[0] == 1 && W > 1;
@@ -139,8 +169,15 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
                 tmp[m] = a.nt_in ? load_once(p) : *p;
             }
 #pragma unroll
-            for (int m = 0; m < 16; ++m) lds[slot[m]] = tmp[m];
+            for (int m = 0; m < 16; ++m) {
+                lds[slot[m]] = tmp[m];
+                if constexpr (PREC == 2) tmax = abs_max(tmp[m], tmax);
+            }
         }
+    }
+    if constexpr (PREC == 2) {
+        tmax = wave_max(tmax);
+        if ((t & 63) == 0) wmax[t >> 6] = tmax;
     }
 
     // A operand fragments of this lane: two 16-row halves, hi and lo parts.
@@ -157,14 +194,18 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
             alo[h][i] = S(float(v - double(float(hi))));
         }
     __syncthreads();
+    // Exact power-of-two scaling of the tile for fp16 (see the file comment).
+    float down = 1.f, up = 1.f;
+    if constexpr (PREC == 2) {
+        float m = 0.f;
+        for (int w = 0; w < (T >> 6); ++w) m = fmaxf(m, wmax[w]);
+        tile_scale(m, down, up);
+    }
 
 #pragma unroll
     for (int s = 0; s < NST; ++s) {
         const int lgns = 4 * s;
         const int ns = 1 << lgns;
-        // Exact power-of-two scaling for fp16 (see the file comment).
-        const int lgscale = PREC == 2 ? (a.pre_lg + lgns) / 2 : 0;
-        const float down = __builtin_ldexpf(1.0f, -lgscale), up = __builtin_ldexpf(1.0f, lgscale);
         V y[GPW][4];
         int bidx[GPW], widx[GPW];
 #pragma unroll
@@ -185,7 +226,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
                     tw.y = -sign * tw.y;
                     x = cmul(x, tw);
                 }
-                const float xr = x.x * down, xi = x.y * down;
+                float xr = x.x, xi = x.y;
+                if (PREC == 2 && s == 0) {
+                    xr *= down;
+                    xi *= down;
+                }
                 const S hr = S(xr), hi_ = S(xi);
                 bhi[2 * i] = hr;
                 bhi[2 * i + 1] = hi_;
@@ -198,8 +243,12 @@ __global__ void __launch_bounds__(kMaxThreads) k_pass_mfma(PassArgs a)
                 acc = Sp::mma(ahi[h], bhi, acc);
                 acc = Sp::mma(ahi[h], blo, acc);
                 acc = Sp::mma(alo[h], bhi, acc);
-                y[grp][2 * h] = mkc(acc[0] * up, acc[1] * up);
-                y[grp][2 * h + 1] = mkc(acc[2] * up, acc[3] * up);
+                if (PREC == 2 && s + 1 == NST) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] *= up;
+                }
+                y[grp][2 * h] = mkc(acc[0], acc[1]);
+                y[grp][2 * h + 1] = mkc(acc[2], acc[3]);
             }
         }
         __syncthreads();
@@ -318,8 +367,10 @@ __device__ __forceinline__ void split_pack(float xr, float xi, uint32_t& hw, uin
 // contraction is done, and one barrier ends the stage.  Padded slot
 // base + r 16^s is pad(base) + r * pstep (pstep = 1 at s = 0, else
 // 16^s * 17 / 16).
+// fp16: the columns hold the tile times `down` (the tile scale), applied as
+// stage 0 reads them; the caller multiplies the result by the inverse.
 template <int LGN, int PREC, bool FWD, typename V8>
-__device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, int pre_lg, int t,
+__device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, float down, int t,
                                                  const V8 (&ahi)[2], const V8 (&alo)[2])
 {
     using Sp = SplitT<PREC>;
@@ -339,9 +390,7 @@ __device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const floa
         const int lgns = 4 * s, ns = 1 << lgns;
         const int pstep = s == 0 ? 1 : ns + (ns >> 4);
         const int tsh = kLgTwBlk - lgns - 4;
-        // Exact power-of-two scaling for fp16 (see the file comment).
-        const int lgscale = PREC == 2 ? (pre_lg + lgns) / 2 : 0;
-        const float down = __builtin_ldexpf(1.0f, -lgscale), up = __builtin_ldexpf(1.0f, lgscale);
+        const float mul = (PREC == 2 && s == 0) ? down : 1.0f;
 #pragma unroll 2
         for (int grp = 0; grp < GPW; ++grp) {
             const int bf = (wave * GPW + grp) * 16 + (lane & 15);
@@ -356,8 +405,8 @@ __device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const floa
                 if (s > 0) x = cmul_fwd_or_conj(x, tw_blk(tl, (jj * r) << tsh), FWD);
                 float xr = x.x, xi = x.y;
                 if constexpr (PREC == 2) {
-                    xr *= down;
-                    xi *= down;
+                    xr *= mul;
+                    xi *= mul;
                 }
                 split_pack<PREC>(xr, xi, bhi.w[i], blo.w[i]);
             }
@@ -367,10 +416,6 @@ __device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const floa
                 acc = Sp::mma(ahi[h], bhi.v, acc);
                 acc = Sp::mma(ahi[h], blo.v, acc);
                 acc = Sp::mma(alo[h], bhi.v, acc);
-                if constexpr (PREC == 2) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c] *= up;
-                }
                 // rows 4g .. 4g+3 of half h: outputs q = 8h + 2g and 8h + 2g + 1
                 const int q = 8 * h + 2 * g;
                 pb[q * pstep] = mkc(acc[0], acc[1]);
@@ -469,6 +514,17 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
         const int i = t + 1024 * k;
         if (i < nt) tl[i] = tab[k];
     }
+    // fp16: the largest |component| of the tile, one slot per wave after the
+    // tables (see the file comment).
+    float* wmax = reinterpret_cast<float*>(tl + nt);
+    float down = 1.f, up = 1.f;
+    if constexpr (PREC == 2) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < E; ++k) m = abs_max(v1[k], abs_max(v0[k], m));
+        m = wave_max(m);
+        if ((t & 63) == 0) wmax[t >> 6] = m;
+    }
     V8 ahi[2], alo[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -479,6 +535,12 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
         for (int m = 0; m < E; ++m) cin[lds_pad(rev16<LGN / 4>(ji + m * TPC))] = vh[m];
         __syncthreads();
         if (h == 0) {
+            if constexpr (PREC == 2) {
+                float m = 0.f;
+#pragma unroll
+                for (int w = 0; w < 16; ++w) m = fmaxf(m, wmax[w]);
+                tile_scale(m, down, up);
+            }
             // A operand fragments of this lane (two 16-row halves of the real
             // 32 x 32 DFT matrix, hi and lo parts) from the omega_16 entries
             // of the in-block table: tl[128 + 8 e] = omega_{2^14}^(1024 e).
@@ -497,10 +559,14 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
                     alo[hh][i] = S(v - float(hi));
                 }
         }
-        mfma_half_stages<LGN, PREC, FWD>(lds, cs, tl, a.pre_lg, t, ahi, alo);
+        mfma_half_stages<LGN, PREC, FWD>(lds, cs, tl, down, t, ahi, alo);
+        // Read back in natural order (fp16: undoing the tile scale).
         const V* cout = lds + uo * cs;
 #pragma unroll
-        for (int m = 0; m < E; ++m) vh[m] = cout[lds_pad(jo + m * TPC)];
+        for (int m = 0; m < E; ++m) {
+            vh[m] = cout[lds_pad(jo + m * TPC)];
+            if constexpr (PREC == 2) vh[m] = mkc(vh[m].x * up, vh[m].y * up);
+        }
     }
 
     const uint32_t ju = uint32_t(jo), uu = uint32_t(uo);

@@ -162,7 +162,7 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         while ((d.size[0] % (int64_t(2) << lg0)) == 0) ++lg0;
     }
     const int eb = int(elem_bytes(fp64));
-    const int table_bytes = (moa::kTwBlkEntries + 256 * d.tw_parts) * eb;
+    const int table_bytes = (moa::kTwBlkEntries + 256 * d.tw_parts + (d.mfma ? moa::kMfmaScaleElems : 0)) * eb;
     auto lds_for = [&](int lgw, bool tile_fast) {
         const int W = 1 << lgw;
         const int lanes = tile_fast ? (W >= 16 ? 1 : 16 / W) : tpc_for(lgw);
@@ -229,7 +229,8 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         d.out_tile_fast = out_tf;
         d.col_stride = moa::lds_col_stride(1 << lgn, std::max(1, 16 / P));
         d.data_elems = P * d.col_stride;
-        d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * (d.tw ? d.tw_parts : 0)) * eb0;
+        d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * (d.tw ? d.tw_parts : 0) +
+                       (d.mfma ? moa::kMfmaScaleElems : 0)) * eb0;
         if (d.lds_bytes > moa::kLdsBytes) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
         d.threads = 1024;
         int64_t blocks = d.size[0] >> lgw_;
@@ -271,8 +272,9 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     const auto cl = lds_for(lgw, d.in_tile_fast);
     d.col_stride = cl.first;
     d.data_elems = (1 << lgw) * cl.first;
-    // LDS: data tile, then the in-block twiddle halves, then the inter-level parts.
-    d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * d.tw_parts) * eb;
+    // LDS: data tile, then the in-block twiddle halves, then the inter-level
+    // parts (then the scale slots of a matrix-core level).
+    d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * d.tw_parts + (d.mfma ? moa::kMfmaScaleElems : 0)) * eb;
     if (d.lds_bytes > moa::kLdsBytes) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
     d.threads = int(threads_for(lgw));
     if (!threads_ok(lgw)) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
@@ -1199,17 +1201,22 @@ moa_status_t moa_fft_exec_level(moa_fft_plan_t p, moa_fft_dir_t dir, int32_t lev
     }
     if (level < 0 || size_t(level) >= p->passes.size()) return MOA_ERR_ARG;
     if (p->host_only) return MOA_ERR_STATE;
-    if (p->ws_bytes && !p->d_ws) return MOA_ERR_STATE;  // planned without a workspace
-    if (!pair_aligned(p->passes[size_t(level)], in, out, true, true)) return MOA_ERR_ARG;
+    const PassDesc& d = p->passes[size_t(level)];
+    if (!pair_aligned(d, in, out, true, true)) return MOA_ERR_ARG;
+    // In place only where the level stores in its load pattern.
+    const size_t P = p->passes.size();
+    if (in == out && p->dims.empty() && P > 1) {
+        const bool last = size_t(level) + 1 == P;
+        const bool blocked = d.out_lgb != moa::kNoBlock || d.out_pair_s || d.out_tile_s;
+        if (last || (level == 0 && blocked)) return MOA_ERR_ARG;
+    }
     moa::PassArgs args[moa::kMaxPasses];
     pass_args(p, int(dir), in, out, p->d_ws, args);
     moa::PassArgs& a = args[size_t(level)];
-    // One level runs from `in` to `out` whatever its position (a lifted plan's
-    // middle levels otherwise read and write the workspace).
-    if (!p->dims.empty()) {
-        a.in = in;
-        a.out = out;
-    }
+    // One level runs from `in` to `out` whatever its position (the middle
+    // levels of a whole execution read and write the workspace).
+    a.in = in;
+    a.out = out;
     return moa::launch_pass(p->fp64, p->passes[size_t(level)], a,
                             static_cast<hipStream_t>(stream)) == hipSuccess
                ? MOA_OK

@@ -79,3 +79,36 @@ def test_config5_sampled_rows():
     assert errs["native"] <= 2e-6 * 20
     assert errs["split_fp16"] <= 2e-6 * 20
     assert errs["split_bf16"] <= 2.0 * 5 * 2.0 ** -16
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("scale,kind", [(1e-4, "uniform"), (1e3, "uniform"), (1e3, "dc"), (1e-4, "dc"),
+                                        (3e4, "dc"), (1.0, "mixed")])
+@pytest.mark.parametrize("n,lift", [(1 << 20, [256, 4096]), (4096, None), (1 << 12, [16, 256])])
+def test_split_input_range(prec, scale, kind, n, lift):
+    """The split levels scale every tile by a power of two from its own data,
+    so their error does not depend on the input's range: tiny inputs keep
+    their low parts out of fp16's subnormal range, large or coherent (DC)
+    inputs do not overflow it.  'dc' is a constant signal plus 1e-3 noise
+    (all energy in one bin, the worst-case growth of every stage); 'mixed'
+    has transforms of amplitude 1e-3 and 1e3 side by side in one batch."""
+    need_gpu()
+    batch = 2
+    x = inputs.uniform_complex((batch, n), seed=n + 7, dtype=np.complex128)
+    if kind == "dc":
+        x = 1.0 + 1e-3 * x
+    if kind == "mixed":
+        x = x * np.array([[1e-3], [1e3]])
+    x = (scale * x).astype(np.complex64)
+    plan = mfft.Plan(n, batch, lift, prec=prec)
+    d = plan.describe()
+    stages = sum(int(np.log2(p["N"])) // 4 for p in d["passes"] if p["mfma"] != "none")
+    t = torch.from_numpy(x).cuda()
+    for name, sign, fn in (("forward", -1, plan.forward), ("adjoint", 1, plan.adjoint)):
+        got = fn(t).cpu().numpy().astype(np.complex128).reshape(batch, n)
+        assert np.isfinite(got).all()
+        want = oracle.fft(x.astype(np.complex128), sign)
+        err = rows_err(got, want)
+        print(f"{prec} {kind} scale {scale:g} n={n} lift={lift} {name}: rel err {err:.3e}", flush=True)
+        assert err <= bound(prec, n, stages)
+    plan.close()
