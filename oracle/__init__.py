@@ -22,6 +22,10 @@ Functions (all on numpy ``complex128`` arrays, sign -1 = forward):
 * :func:`fft_batch`, :func:`fft_packed` -- contiguous and uneven batches.
 * :func:`fftn` -- the multi-dimensional DFT, the 1-D oracle along each axis.
 * :func:`weighted_power_loss` -- L = sum_k w_k |F x|_k^2 and its gradient.
+
+``density.py`` holds the density-matrix gating oracle of Ch. 6 (numpy,
+complex128): the gate by its definition G rho G^H and by the block-diagonal
+route through the hyper-cube transpose of ``moa.py``.
 """
 from __future__ import annotations
 

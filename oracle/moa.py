@@ -173,3 +173,60 @@ def hyper(A: MArray) -> MArray:
 def reshape_transpose(A: MArray, r: int, c: int) -> MArray:
     """<r c> rho^ (transpose (<r c> rho^ A))  (Ch. 3, Eq. abstract)."""
     return reshape([r, c], transpose(reshape([r, c], A)))
+
+
+def gate_transpose_vector(n: int, gated_bits: Sequence[int]) -> List[int]:
+    """Transpose vector t of Ch. 6 ("The Algorithm", "From qubits to
+    permutation vector") for an n-qubit density matrix viewed as the
+    hyper-cube D_h of 2n axes (the n row bits, then the n column bits, each
+    most significant first; bits are numbered from the right, axes from the
+    left, so bit b of a row index is axis n - 1 - b).  t lists, for the row
+    half and then (offset by n) the column half, the axes of the bits that
+    are not gated followed by the axes of the gated bits, each group in
+    increasing axis order -- the arrangement the paper reaches by its swaps.
+    Entry k names the axis of D_h that becomes axis k of the block-diagonal
+    view (reading: the swaps build the list of source axes in their new
+    order), so the view is (inverse t) transpose D_h in the transpose of
+    Ch. 2; the gated bits are then the low bits of both indices and the
+    2^q x 2^q blocks on the diagonal hold the gated sub-matrices.  For the
+    involutive vector of the xaxb example the two readings coincide."""
+    n = int(n)
+    gated = sorted({int(b) for b in gated_bits})
+    if len(gated) != len(list(gated_bits)) or any(not 0 <= b < n for b in gated):
+        raise ValueError("gated bits must be distinct positions in [0, n)")
+    gated_axes = [n - 1 - b for b in gated]
+    free = [ax for ax in range(n) if ax not in gated_axes]
+    half = free + sorted(gated_axes)
+    return half + [ax + n for ax in half]
+
+
+def hypercube_transpose(values: Sequence, t: Sequence[int]) -> List:
+    """t transpose (<2 ... 2> rho^ values), ravelled (Ch. 6, "Final Expression
+    and Normal Form": i psi (t transpose D_h) = i[t] psi D_h)."""
+    A = hyper(MArray([len(values)], list(values)))
+    return transpose(A, t).ravel
+
+
+def hypercube_source_offsets(m: int, t: Sequence[int]) -> List[int]:
+    """The generic normal form of Ch. 6: for every index i of t transpose D_h
+    (in lexical order), the offset gamma(i[t]; s) of the element it names in
+    D_h, s = <2 ... 2> of m axes."""
+    s = [2] * int(m)
+    out = []
+    for i in indices(s):
+        out.append(gamma(s, [i[int(t[k])] for k in range(int(m))]))
+    return out
+
+
+def inverse_permutation(t: Sequence[int]) -> List[int]:
+    """s with s[t[k]] = k."""
+    s = [0] * len(t)
+    for k, v in enumerate(t):
+        s[int(v)] = k
+    return s
+
+
+def block_diagonal_view(values: Sequence, n: int, gated_bits: Sequence[int]) -> List:
+    """The block-diagonal arrangement of Ch. 6 of a 2^n x 2^n matrix given by
+    its ravel: (inverse t) transpose D_h, t = gate_transpose_vector."""
+    return hypercube_transpose(values, inverse_permutation(gate_transpose_vector(n, gated_bits)))
