@@ -8,7 +8,7 @@ transpose folded into the store).  A step is one full transform; inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
-                    [--extras uneven,fwd_adj,split_mfma,tuned,c128]
+                    [--extras uneven,fwd_adj,split_mfma,tuned,hypercube,c128]
 
 Throughput is 5 n log2(n) / t (GFLOP/s).  The roofline block reports the
 dominant kernel (the slower of the two level launches, each timed in its place
@@ -394,6 +394,46 @@ def extras(args, torch, np, mfft, inputs):
                             "candidates": best["tried"]}
         del xt, yt
 
+    if want("hypercube"):
+        # Ch. 6 workload: a 13-qubit complex64 density matrix (2^26 elements,
+        # 512 MiB).  The hyper-cube transpose to its block-diagonal view for
+        # two gated qubits (pure movement: read + write of every element), and
+        # the in-place gates rho <- G rho G^H by direct indexing (the same
+        # bytes), against a plain device copy of the same buffer.
+        from paper_0803_2386_amd import hypercube as hcube
+        nq = 13
+        N = 1 << nq
+        rho = inputs.device_uniform_complex(N * N, args.seed + 4, torch.complex64, dev).view(N, N)
+        tgt = torch.empty_like(rho)
+        nbytes = 2 * 8 * N * N
+        rec = {"qubits": nq, "elements": N * N, "bytes_per_launch": nbytes}
+        hreps = max(5, reps // 2)
+
+        def rate(ms):
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            return {"ms": round(ms, 5), "hbm_gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        tgt.copy_(rho)
+        rec["device_copy"] = rate(time_events(lambda: tgt.copy_(rho), hreps, torch))
+        for gated in ([0, 2], [11, 12]):
+            t = hcube.block_diagonal_transpose_vector(nq, gated)
+            hcube.hypercube_transpose(rho.view(-1), t, out=tgt.view(-1))
+            r = rate(time_events(lambda: hcube.hypercube_transpose(rho.view(-1), t, out=tgt.view(-1)), hreps, torch))
+            r["cold_ms_median"] = round(cold_step_ms(
+                lambda: hcube.hypercube_transpose(rho.view(-1), t, out=tgt.view(-1)), 5, torch, np), 5)
+            r["t"] = t
+            rec["transpose_gated_%d_%d" % tuple(gated)] = r
+        rng = np.random.default_rng(args.seed)
+        for gated in ([0, 2], [11, 12], [0, 1, 2, 3]):
+            k = 1 << len(gated)
+            z = rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))
+            U = torch.from_numpy(np.linalg.qr(z)[0].astype(np.complex64)).to(dev)
+            hcube.density_gate(tgt, U, gated)
+            r = rate(time_events(lambda: hcube.density_gate(tgt, U, gated), hreps, torch))
+            r["cold_ms_median"] = round(cold_step_ms(lambda: hcube.density_gate(tgt, U, gated), 5, torch, np), 5)
+            rec["gate_" + "_".join(str(b) for b in gated)] = r
+        ex["hypercube_13_qubits_c64"] = rec
+        del rho, tgt
+
     if want("c128"):
         # Latency of the complex128 n = 2^10 transform (single workgroup).
         p = mfft.Plan(1 << 10, 1, None, dtype=torch.complex128)
@@ -535,7 +575,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error statement)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extra workloads: uneven, fwd_adj, split_mfma, tuned, c128 (default all)")
+                    help="comma list of extra workloads: uneven, fwd_adj, split_mfma, tuned, hypercube, c128 (default all)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device copy of the same buffer (reference for HBM counters)")
     args = ap.parse_args()

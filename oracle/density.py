@@ -71,7 +71,7 @@ def apply_gate_blocks(rho, U, gated_bits: Sequence[int]) -> np.ndarray:
     src = np.asarray(moa_source_offsets_fast(2 * n, t))
     view = rho.reshape(-1)[src].reshape(N >> q, 1 << q, N >> q, 1 << q)
     U = np.asarray(U, np.complex128)
-    out_view = np.einsum("ak,rksl,bl->rasb", U, view, U.conj())
+    out_view = np.einsum("ak,rksl,bl->rasb", U, view, U.conj(), optimize=True)
     out = np.empty(N * N, np.complex128)
     out[src] = out_view.reshape(-1)
     return out.reshape(N, N)

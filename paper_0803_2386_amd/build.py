@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmoa_fft.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["plan.cpp", "fft_kernels.hip", "fft_pair.hip", "fft_small.hip", "fft_batched.hip", "fft_mfma.hip",
-           "scratch.hip"]
+           "scratch.hip", "hypercube.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -46,6 +46,7 @@ EXPORTED = [
     "moa_fft_plan_batched", "moa_fft_plan_batched_tuned",
     "moa_fft_exec", "moa_fft_exec_noalloc", "moa_fft_exec_level", "moa_fft_num_levels", "moa_fft_workspace_size", "moa_fft_describe", "moa_fft_describe_size",
     "moa_fft_destroy", "moa_fft_status_string", "moa_fft_max_block",
+    "moa_hypercube_transpose", "moa_density_gate",
 ]
 
 
@@ -100,6 +101,8 @@ def load() -> ctypes.CDLL:
         "moa_fft_destroy": ([P], E),
         "moa_fft_status_string": ([E], ctypes.c_char_p),
         "moa_fft_max_block": ([E], I64),
+        "moa_hypercube_transpose": ([I32, ctypes.POINTER(I32), I32, P, P, P], E),
+        "moa_density_gate": ([I32, I32, ctypes.POINTER(I32), P, E, P, P], E),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -235,3 +238,30 @@ def moa_fft_destroy(plan) -> None:
     st = load().moa_fft_destroy(plan)
     if st != MOA_OK:
         raise MoaError(st, "moa_fft_destroy")
+
+
+def _i32_array(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_int32 * max(1, len(vals)))(*vals), len(vals)
+
+
+def moa_hypercube_transpose(t, elem_bytes: int, in_ptr: int, out_ptr: int, stream: int = 0, rank=None) -> None:
+    """out = t transpose (<2 ... 2> reshape in) on 2^len(t) elements (see
+    include/moa_hypercube.h); rank defaults to len(t)."""
+    arr, m = _i32_array(t)
+    st = load().moa_hypercube_transpose(int(m if rank is None else rank), arr, int(elem_bytes),
+                                        ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream))
+    if st != MOA_OK:
+        raise MoaError(st, "moa_hypercube_transpose")
+
+
+def moa_density_gate(n_qubits: int, gated_bits, gate_ptr: int, dtype: int, rho_ptr: int, stream: int = 0,
+                     q=None) -> None:
+    """rho <- G rho G^H in place for the gate U (device, 2^q x 2^q) on the
+    qubits gated_bits (see include/moa_hypercube.h); q defaults to
+    len(gated_bits)."""
+    arr, k = _i32_array(gated_bits)
+    st = load().moa_density_gate(int(n_qubits), int(k if q is None else q), arr, ctypes.c_void_p(gate_ptr),
+                                 int(dtype), ctypes.c_void_p(rho_ptr), ctypes.c_void_p(stream))
+    if st != MOA_OK:
+        raise MoaError(st, "moa_density_gate")

@@ -1,0 +1,268 @@
+// Hyper-cube kernels (Ch. 6, "Density Matrix Operations for a Quantum
+// Computer"; Ch. 4, "Reordering the Data"): the generalized transpose of an
+// array viewed as a hyper-cube of 2-element axes, and the gating of a
+// density matrix through the block-diagonal view of that transpose.
+//
+// Both kernels move tiles through LDS.  An element's offset is a string of
+// bits; a transpose of the hyper-cube permutes those bits.  A tile is the set
+// of elements whose offsets differ only in a chosen set of bit positions
+// (the tile bits); the other bits, taken from the workgroup index, fix the
+// tile.  The tile bits include the low bits of the source offset (so the
+// tile's loads are runs of 256 contiguous bytes or more) and the low bits of
+// the destination offset (so are its stores); the tile waits in LDS between
+// the two.  Bit-deposit maps (tile bit j -> offset bit) come in the kernel
+// arguments: per thread, the deposit of its thread index is computed once,
+// and the deposit of each of its repeat indices is a table entry.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "../../include/moa_hypercube.h"
+#include "hypercube_plan.h"
+
+namespace moa_hc {
+
+__device__ __forceinline__ int pad(int i) { return i + (i >> 5); }  // pad_slot on the device
+
+// ---------------------------------------------------------------------------
+// Transpose: out[o] = in[src(o)], src permuting the bits of o.
+// ---------------------------------------------------------------------------
+
+// PER elements of the tile per thread (PER * threads = tile elements).
+template <typename T, int PER>
+__global__ void __launch_bounds__(kThreads) k_hc_transpose(TransArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    const T* __restrict__ in = reinterpret_cast<const T*>(a.in);
+    T* __restrict__ out = reinterpret_cast<T*>(a.out);
+    const uint32_t t = threadIdx.x;
+    // Tile offsets (uniform).
+    const uint64_t tile = blockIdx.x;
+    uint64_t ob = 0, ib = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxRankBits; ++j) {
+        if (j < a.nt_bits) {
+            const uint64_t bit = (tile >> j) & 1u;
+            ob |= bit << a.nt_out[j];
+            ib |= bit << a.nt_in[j];
+        }
+    }
+    // Deposits of the thread index.
+    uint64_t in_lo = 0, out_lo = 0;
+    uint32_t lds_lo = 0;
+#pragma unroll
+    for (int j = 0; j < kLgThreads; ++j) {
+        if (j < a.lg_threads) {
+            const uint32_t bit = (t >> j) & 1u;
+            in_lo |= uint64_t(bit) << a.ld_in_lo[j];
+            lds_lo |= bit << a.ld_lds_lo[j];
+            out_lo |= uint64_t(bit) << a.st_out_lo[j];
+        }
+    }
+    // Load the tile (all loads in flight before the LDS stores).
+    T v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = in[ib + in_lo + uint64_t(a.ld_in_hi[r])];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) lds[pad(int(lds_lo) + a.ld_lds_hi[r])] = v[r];
+    __syncthreads();
+    // Store it in the destination's order.
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = lds[pad(int(t) + (r << a.lg_threads))];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) out[ob + out_lo + uint64_t(a.st_out_hi[r])] = v[r];
+}
+
+// ---------------------------------------------------------------------------
+// Density-matrix gate: every 2^q x 2^q block B of the block-diagonal view
+// becomes U B U^H, read and written in place through the normal form.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float2 cmadd(float2 acc, float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+__device__ __forceinline__ double2 cmadd(double2 acc, double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+// acc + a conj(b)
+__device__ __forceinline__ float2 cmadd_conj(float2 acc, float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(a.y, b.x, fmaf(-a.x, b.y, acc.y)));
+}
+__device__ __forceinline__ double2 cmadd_conj(double2 acc, double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.y, b.x, fma(-a.x, b.y, acc.y)));
+}
+
+template <typename C, int Q, int PER>
+__global__ void __launch_bounds__(kThreads) k_density_gate(GateArgs a)
+{
+    constexpr int D = 1 << Q;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = reinterpret_cast<C*>(smem);
+    const int tile_elems = 1 << a.tile_bits;
+    C* ul = lds + pad(tile_elems);   // U, D x D
+    C* __restrict__ rho = reinterpret_cast<C*>(a.rho);
+    const uint32_t t = threadIdx.x;
+    const int nthr = 1 << a.lg_threads;
+    const uint64_t tile = blockIdx.x;
+    uint64_t base = 0;
+#pragma unroll
+    for (int j = 0; j < 2 * 15; ++j)
+        if (j < a.nt_bits) base |= ((tile >> j) & 1u) << a.nt_addr[j];
+    uint64_t lo = 0;
+#pragma unroll
+    for (int j = 0; j < kLgThreads; ++j)
+        if (j < a.lg_threads) lo |= uint64_t((t >> j) & 1u) << a.lo_addr[j];
+    C v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = rho[base + lo + uint64_t(a.hi_addr[r])];
+    for (int i = int(t); i < D * D; i += nthr) ul[i] = reinterpret_cast<const C*>(a.gate)[i];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) lds[pad(int(t) + (r << a.lg_threads))] = v[r];
+    // LDS offsets of U's row and column indices (uniform).
+    int roff[D], coff[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        int ro = 0, co = 0;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+            if ((k >> b) & 1) {
+                ro |= 1 << a.row_lds[b];
+                co |= 1 << a.col_lds[b];
+            }
+        }
+        roff[k] = ro;
+        coff[k] = co;
+    }
+    __syncthreads();
+    const int nblk = 1 << a.blk_bits;
+    const int tasks = nblk * D;
+    // Phase 1: column l of block beta: B[., l] <- U B[., l].
+    for (int task = int(t); task < tasks; task += nthr) {
+        const int beta = task & (nblk - 1), l = task >> a.blk_bits;
+        int bo = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxTileBits; ++j)
+            if (j < a.blk_bits) bo |= ((beta >> j) & 1) << a.blk_lds[j];
+        const int c0 = bo + coff[l];
+        C x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = lds[pad(c0 + roff[k])];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            C acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc = cmadd(acc, ul[i * D + k], x[k]);
+            lds[pad(c0 + roff[i])] = acc;
+        }
+    }
+    __syncthreads();
+    // Phase 2: row i of block beta: T[i, .] <- T[i, .] U^H.
+    for (int task = int(t); task < tasks; task += nthr) {
+        const int beta = task & (nblk - 1), i = task >> a.blk_bits;
+        int bo = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxTileBits; ++j)
+            if (j < a.blk_bits) bo |= ((beta >> j) & 1) << a.blk_lds[j];
+        const int r0 = bo + roff[i];
+        C x[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) x[l] = lds[pad(r0 + coff[l])];
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            C acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc = cmadd_conj(acc, x[l], ul[b * D + l]);
+            lds[pad(r0 + coff[b])] = acc;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = lds[pad(int(t) + (r << a.lg_threads))];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) rho[base + lo + uint64_t(a.hi_addr[r])] = v[r];
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_transpose(const TransArgs& a, int64_t tiles, int lds_bytes, hipStream_t s)
+{
+    const dim3 g(static_cast<unsigned>(tiles)), b(1u << a.lg_threads);
+    switch (a.tile_bits - a.lg_threads) {
+        case 0: hipLaunchKernelGGL((k_hc_transpose<T, 1>), g, b, lds_bytes, s, a); break;
+        case 1: hipLaunchKernelGGL((k_hc_transpose<T, 2>), g, b, lds_bytes, s, a); break;
+        case 2: hipLaunchKernelGGL((k_hc_transpose<T, 4>), g, b, lds_bytes, s, a); break;
+        case 3: hipLaunchKernelGGL((k_hc_transpose<T, 8>), g, b, lds_bytes, s, a); break;
+        case 4: hipLaunchKernelGGL((k_hc_transpose<T, 16>), g, b, lds_bytes, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename C, int Q>
+hipError_t launch_gate_q(const GateArgs& a, dim3 g, dim3 b, int lds_bytes, hipStream_t s)
+{
+    switch (a.tile_bits - a.lg_threads) {
+        case 0: hipLaunchKernelGGL((k_density_gate<C, Q, 1>), g, b, lds_bytes, s, a); break;
+        case 1: hipLaunchKernelGGL((k_density_gate<C, Q, 2>), g, b, lds_bytes, s, a); break;
+        case 2: hipLaunchKernelGGL((k_density_gate<C, Q, 4>), g, b, lds_bytes, s, a); break;
+        case 3: hipLaunchKernelGGL((k_density_gate<C, Q, 8>), g, b, lds_bytes, s, a); break;
+        case 4: hipLaunchKernelGGL((k_density_gate<C, Q, 16>), g, b, lds_bytes, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename C>
+hipError_t launch_gate(int q, const GateArgs& a, int64_t tiles, int lds_bytes, hipStream_t s)
+{
+    const dim3 g(static_cast<unsigned>(tiles)), b(1u << a.lg_threads);
+    switch (q) {
+        case 1: return launch_gate_q<C, 1>(a, g, b, lds_bytes, s);
+        case 2: return launch_gate_q<C, 2>(a, g, b, lds_bytes, s);
+        case 3: return launch_gate_q<C, 3>(a, g, b, lds_bytes, s);
+        default: return launch_gate_q<C, 4>(a, g, b, lds_bytes, s);
+    }
+}
+
+}  // namespace moa_hc
+
+using namespace moa_hc;
+
+extern "C" moa_status_t moa_hypercube_transpose(int32_t rank, const int32_t* t, int32_t elem_bytes, const void* in,
+                                                void* out, void* stream)
+{
+    TransArgs a;
+    Launch L;
+    if (const moa_status_t st = plan_transpose(rank, t, elem_bytes, in, out, a, L)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (elem_bytes == 4) e = launch_transpose<uint32_t>(a, L.tiles, L.lds_bytes, s);
+    else if (elem_bytes == 8) e = launch_transpose<uint2>(a, L.tiles, L.lds_bytes, s);
+    else e = launch_transpose<uint4>(a, L.tiles, L.lds_bytes, s);
+    return e == hipSuccess ? MOA_OK : MOA_ERR_HIP;
+}
+
+extern "C" moa_status_t moa_density_gate(int32_t n_qubits, int32_t q, const int32_t* gated_bits, const void* gate,
+                                         moa_fft_dtype_t dtype, void* rho, void* stream)
+{
+    GateArgs a;
+    Launch L;
+    if (const moa_status_t st = plan_gate(n_qubits, q, gated_bits, gate, dtype, rho, a, L)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = dtype == MOA_C128 ? launch_gate<double2>(q, a, L.tiles, L.lds_bytes, s)
+                                           : launch_gate<float2>(q, a, L.tiles, L.lds_bytes, s);
+    return e == hipSuccess ? MOA_OK : MOA_ERR_HIP;
+}

@@ -30,7 +30,8 @@ def built_library():
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "moa_fft.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     return sorted(set(re.findall(r"^\s*(?:const char\*|moa_status_t|int64_t)\s+(moa_\w+)\s*\(", text, re.M)))
 
 
@@ -490,3 +491,39 @@ def test_stale_and_double_destroyed_handles_are_rejected():
     junk = ctypes.create_string_buffer(256)
     assert lib.moa_fft_destroy(ctypes.cast(junk, ctypes.c_void_p)) == capi.MOA_ERR_STATE
     assert lib.moa_fft_num_levels(ctypes.cast(junk, ctypes.c_void_p), ctypes.byref(lv)) == capi.MOA_ERR_STATE
+
+
+def test_hypercube_entry_points_validate_on_the_host():
+    """Both hyper-cube calls refuse invalid arguments before any HIP call."""
+    lib = capi.load()
+    P = ctypes.c_void_p
+    a, b = P(1 << 20), P(1 << 30)
+    perm = (ctypes.c_int32 * 4)(2, 0, 3, 1)
+    bad = (ctypes.c_int32 * 4)(2, 0, 2, 1)
+    T = lib.moa_hypercube_transpose
+    assert T(4, None, 8, a, b, None) == capi.MOA_ERR_NULL
+    assert T(4, perm, 8, None, b, None) == capi.MOA_ERR_NULL
+    assert T(0, perm, 8, a, b, None) == capi.MOA_ERR_SIZE
+    assert T(35, perm, 8, a, b, None) == capi.MOA_ERR_SIZE
+    assert T(4, bad, 8, a, b, None) == capi.MOA_ERR_ARG
+    assert T(4, perm, 12, a, b, None) == capi.MOA_ERR_ARG
+    assert T(4, perm, 8, P((1 << 20) + 8), b, None) == capi.MOA_ERR_ARG   # misaligned
+    assert T(4, perm, 8, a, P((1 << 20) + 64), None) == capi.MOA_ERR_ARG  # overlapping
+    g = (ctypes.c_int32 * 2)(0, 2)
+    G = lib.moa_density_gate
+    assert G(4, 2, None, a, capi.MOA_C64, b, None) == capi.MOA_ERR_NULL
+    assert G(4, 2, g, None, capi.MOA_C64, b, None) == capi.MOA_ERR_NULL
+    assert G(16, 2, g, a, capi.MOA_C64, b, None) == capi.MOA_ERR_SIZE
+    assert G(4, 5, g, a, capi.MOA_C64, b, None) == capi.MOA_ERR_SIZE
+    assert G(1, 2, g, a, capi.MOA_C64, b, None) == capi.MOA_ERR_SIZE
+    assert G(4, 2, (ctypes.c_int32 * 2)(1, 1), a, capi.MOA_C64, b, None) == capi.MOA_ERR_ARG
+    assert G(4, 2, (ctypes.c_int32 * 2)(0, 4), a, capi.MOA_C64, b, None) == capi.MOA_ERR_ARG
+    assert G(4, 2, g, a, 7, b, None) == capi.MOA_ERR_DTYPE
+    assert G(4, 2, g, a, capi.MOA_C64, P((1 << 30) + 8), None) == capi.MOA_ERR_ARG
+
+
+def test_block_diagonal_transpose_vector_is_the_inverse_of_the_printed_one():
+    from paper_0803_2386_amd import hypercube
+    for n, gated in [(4, [0, 2]), (4, [1, 2]), (6, [5, 0, 3]), (3, [0])]:
+        printed = moa.gate_transpose_vector(n, gated)
+        assert hypercube.block_diagonal_transpose_vector(n, gated) == moa.inverse_permutation(printed)

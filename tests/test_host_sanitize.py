@@ -45,3 +45,21 @@ def test_planner_and_oracle_under_asan_ubsan(tmp_path):
     res = _run([exe], env=env, timeout=600)
     assert "all paths clean" in res.stdout
     assert "runtime error" not in res.stderr and "Sanitizer" not in res.stderr, res.stderr
+
+
+@pytest.mark.timeout(900)
+def test_hypercube_kernel_addressing_on_the_cpu(tmp_path):
+    """The hyper-cube kernels' index arithmetic, run for every workgroup and
+    thread on the CPU from the arguments the host planner fills
+    (tests/host_sanitize/hypercube_emul.cpp): every global offset inside the
+    array, every LDS slot inside the allocation and written once before it
+    is read, and the result equal to the definition (the bit permutation of
+    the transpose; G rho G^H of the gate), under ASan/UBSan."""
+    if not shutil.which("g++"):
+        pytest.skip("gcc toolchain missing")
+    exe = str(tmp_path / "hc_emul")
+    _run(["g++", "-std=c++17"] + SAN + ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+                                        os.path.join(HERE, "hypercube_emul.cpp"), "-o", exe])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+    res = _run([exe], env=env, timeout=600)
+    assert "all cases clean" in res.stdout
