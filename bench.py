@@ -295,6 +295,8 @@ def extras(args, torch, np, mfft, inputs):
                 p.forward(xb, out=ob)
             ms = time_events(lambda: p.forward(xb, out=ob), reps, torch)
             rec[name] = entry(ms, p)
+            if name in ("tuned", "tuned_graph", "per_size"):
+                rec[name]["cold_ms_median"] = round(cold_step_ms(lambda: p.forward(xb, out=ob), 7, torch, np), 5)
             if name == "tuned_graph":
                 xs, ys = xb.cpu().numpy(), ob.cpu().numpy()
                 samples["uneven_batch"] = [(xs[offs[i]:offs[i + 1]], ys[offs[i]:offs[i + 1]], 2e-6 * math.log2(sizes[i]))
@@ -337,8 +339,16 @@ def extras(args, torch, np, mfft, inputs):
             p.adjoint(ya, out=za)
         fwd_adj()
         ms = time_events(fwd_adj, reps, torch)
+        lv = level_times_in_chain(p, xa, ya, reps, torch)
+        d = p.describe()
+        gbs = 4 * 16 * n * B / (ms * 1e-3) / 1e9
         ex["fwd_adj_b256_2^16"] = {"ms": round(ms, 5), "gflops": round(2 * gflops(n, B, ms * 1e-3), 1),
-                                   "hbm_gbs": round(4 * 16 * n * B / (ms * 1e-3) / 1e9, 1)}
+                                   "hbm_gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                   "cold_ms_median": round(cold_step_ms(fwd_adj, 7, torch, np), 5),
+                                   "forward_level_ms": [round(v, 5) for v in lv],
+                                   "forward_level_frac_hbm_peak": [
+                                       round(16 * n * B / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for v in lv],
+                                   "kernels": [kernel_name(q) for q in d["passes"]]}
         p.close()
         del xa, ya, za
 
@@ -360,7 +370,10 @@ def extras(args, torch, np, mfft, inputs):
             levels = len(d["passes"])
             r = {"ms": round(ms, 4), "gflops": round(gflops(n, B, ms * 1e-3), 1),
                  "hbm_gbs": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9, 1),
-                 "level_ms": [round(v, 4) for v in lv], "kernels": [kernel_name(q) for q in d["passes"]]}
+                 "frac_hbm_peak": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "level_ms": [round(v, 4) for v in lv],
+                 "level_frac_hbm_peak": [round(16 * n * B / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for v in lv],
+                 "kernels": [kernel_name(q) for q in d["passes"]]}
             stages = sum(int(math.log2(q["N"])) // 4 for q in d["passes"] if q["mfma"] != "none")
             if stages:
                 # 6 MFMA 16x16x32 per 16 butterflies of a stage: 384 flops a point.
@@ -393,6 +406,33 @@ def extras(args, torch, np, mfft, inputs):
                             "gflops": round(gflops(n, 1, ms * 1e-3), 1), "tuner_ms": round(best["ms"], 5),
                             "candidates": best["tried"]}
         del xt, yt
+
+    if want("nd"):
+        # Multi-dimensional transforms of 2^24 complex64 points: 4096 x 4096
+        # (two axis launches) and 256^3 (three), both through the level kernels.
+        for dims in ((4096, 4096), (256, 256, 256)):
+            p = mfft.NDPlan(dims, 1)
+            N = 1 << 24
+            xn = inputs.device_uniform_complex(N, args.seed + 5, torch.complex64, dev)
+            yn = torch.empty_like(xn)
+            for _ in range(3):
+                p.forward(xn, out=yn)
+            ms = time_events(lambda: p.forward(xn, out=yn), reps, torch)
+            lv = level_times_in_chain(p, xn, yn, reps, torch)
+            d = p.describe()
+            dom = int(np.argmax(lv))
+            ach = 16 * N / (lv[dom] * 1e-3) / 1e9
+            ex["nd_" + "x".join(str(v) for v in dims)] = {
+                "ms": round(ms, 5), "gflops": round(gflops(N, 1, ms * 1e-3), 1),
+                "hbm_gbs": round(len(lv) * 16 * N / (ms * 1e-3) / 1e9, 1),
+                "cold_ms_median": round(cold_step_ms(lambda: p.forward(xn, out=yn), 7, torch, np), 5),
+                "level_ms": [round(v, 5) for v in lv], "kernels": [kernel_name(q) for q in d["passes"]],
+                "roofline": {"kernel": kernel_name(d["passes"][dom]), "achieved_gbs": round(ach, 1),
+                             "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": 16 * N}}
+            xs = xn.cpu().numpy().reshape(dims)
+            samples["nd_" + "x".join(str(v) for v in dims)] = {"x": xs, "y": yn.cpu().numpy().reshape(dims)}
+            p.close()
+            del xn, yn
 
     if want("hypercube"):
         # Ch. 6 workload: a 13-qubit complex64 density matrix (2^26 elements,
@@ -556,6 +596,13 @@ def cpu_baseline_leg(args, np, result, sample, samples):
     if not ex:
         return
     errs = {}
+    for name in [k for k in samples if k.startswith("nd_")]:
+        nd = samples.pop(name)
+        xs = nd["x"].astype(np.complex128)
+        want = oracle.fftn(xs, xs.ndim)
+        e = float(np.linalg.norm(nd["y"].astype(np.complex128) - want) / np.linalg.norm(want))
+        tol = 2e-6 * math.log2(xs.size)
+        errs[name] = {"rel_l2_max": e, "transforms": 1, "tolerance": tol, "pass": e <= tol}
     for name, cases in samples.items():
         worst, ok = 0.0, True
         for xs, ys, tol in cases:
@@ -564,6 +611,77 @@ def cpu_baseline_leg(args, np, result, sample, samples):
             ok = ok and e <= tol
         errs[name] = {"rel_l2_max": worst, "transforms": len(cases), "tolerance": cases[0][2], "pass": ok}
     ex["error_vs_fp64_oracle"] = errs
+
+
+def profile_run(args, torch, np, mfft, inputs):
+    """Launch one workload's kernels W + K times and nothing else (no tuner,
+    no oracle), then one 128 MiB device copy, so a rocprofv3 kernel trace or
+    counter run sees exactly those dispatches."""
+    dev = torch.device("cuda", 0)
+    w = args.profile
+    free = []
+    if w == "headline":
+        n = 1 << 24
+        x = inputs.device_uniform_complex(n, args.seed, torch.complex64, dev)
+        y = torch.empty_like(x)
+        p = mfft.Plan(n, 1, [4096, 4096])
+        fn = lambda: p.forward(x, out=y)  # noqa: E731
+    elif w == "uneven":
+        sizes = [int(s) for s in inputs.uneven_sizes(8192, 6, 14, seed=args.seed)]
+        x = inputs.device_uniform_complex(sum(sizes), args.seed, torch.complex64, dev)
+        y = torch.empty_like(x)
+        p = mfft.BatchedPlan(sizes, tuning={"persistent_blocks": args.grid})
+        fn = lambda: p.forward(x, out=y)  # noqa: E731
+    elif w == "fwd_adj":
+        n, B = 1 << 16, 256
+        x = inputs.device_uniform_complex(n * B, args.seed + 1, torch.complex64, dev)
+        y, z = torch.empty_like(x), torch.empty_like(x)
+        p = mfft.Plan(n, B, [256, 256])
+        free.append(z)
+
+        def fn():
+            p.forward(x, out=y)
+            p.adjoint(y, out=z)
+    elif w.startswith("split_"):
+        n, B = 1 << 20, 256
+        x = inputs.device_uniform_complex(n * B, args.seed + 3, torch.complex64, dev)
+        y = torch.empty_like(x)
+        p = mfft.Plan(n, B, [256, 4096], prec="native" if w == "split_native" else w)
+        fn = lambda: p.forward(x, out=y)  # noqa: E731
+    elif w in ("nd2", "nd3"):
+        dims = (4096, 4096) if w == "nd2" else (256, 256, 256)
+        x = inputs.device_uniform_complex(1 << 24, args.seed + 5, torch.complex64, dev)
+        y = torch.empty_like(x)
+        p = mfft.NDPlan(dims, 1)
+        fn = lambda: p.forward(x, out=y)  # noqa: E731
+    elif w in ("hc_transpose", "hc_gate"):
+        from paper_0803_2386_amd import hypercube as hcube
+        N = 1 << 13
+        x = inputs.device_uniform_complex(N * N, args.seed + 4, torch.complex64, dev).view(N, N)
+        y = torch.empty_like(x)
+        p = None
+        if w == "hc_transpose":
+            t = hcube.block_diagonal_transpose_vector(13, [0, 2])
+            fn = lambda: hcube.hypercube_transpose(x.view(-1), t, out=y.view(-1))  # noqa: E731
+        else:
+            U = torch.eye(4, dtype=torch.complex64, device=dev)
+            fn = lambda: hcube.density_gate(y, U, [0, 2])  # noqa: E731
+    else:
+        raise SystemExit(f"bench.py: unknown --profile workload {w!r}")
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        fn()
+    torch.cuda.synchronize()
+    ref = torch.empty(1 << 24, dtype=torch.complex64, device=dev)
+    src = torch.ones_like(ref)
+    ref.copy_(src)
+    torch.cuda.synchronize()
+    if p is not None:
+        p.close()
+    print(f"[bench] profile {w}: {args.warmup} + {args.steps} launches, then a 128 MiB copy", file=sys.stderr,
+          flush=True)
 
 
 def main():
@@ -575,7 +693,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error statement)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extra workloads: uneven, fwd_adj, split_mfma, tuned, hypercube, c128 (default all)")
+                    help="comma list of extra workloads: uneven, fwd_adj, split_mfma, tuned, nd, hypercube, c128 "
+                         "(default all)")
+    ap.add_argument("--profile", default=None,
+                    help="kernel-only run for rocprofv3: warm-up, then --steps launches of one workload's kernels "
+                         "(headline, uneven, fwd_adj, split_native, split_bf16, split_fp16, nd2, nd3, hc_transpose, "
+                         "hc_gate), then a device copy of 128 MiB (the counters' reference); prints nothing else")
+    ap.add_argument("--grid", type=int, default=1536,
+                    help="--profile uneven: workgroups of the fused launch (the tuner's usual pick)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device copy of the same buffer (reference for HBM counters)")
     args = ap.parse_args()
@@ -591,6 +716,9 @@ def main():
     from paper_0803_2386_amd import inputs
 
     torch.cuda.set_device(torch.device("cuda", 0))
+    if args.profile:
+        profile_run(args, torch, np, mfft, inputs)
+        return
     result, sample = headline(args, torch, np, mfft, inputs)
     samples = {}
     if not args.no_extras:
