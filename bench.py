@@ -406,6 +406,31 @@ def extras(args, torch, np, mfft, inputs):
                             "gflops": round(gflops(n, 1, ms * 1e-3), 1), "tuner_ms": round(best["ms"], 5),
                             "candidates": best["tried"]}
         del xt, yt
+        # The register radix as a tuning dimension (Ch. 1, "Performance of the
+        # General-Radix FFT"): 1024 transforms of 2^14 points, the tuner's
+        # schedule against the fixed radix-16 one, timed the same way.
+        n, B = 1 << 14, 1024
+        with tempfile.TemporaryDirectory() as td:
+            os.environ["MOA_FFT_TUNE_CACHE"] = os.path.join(td, "tune.json")
+            best = tune.tune(n, B, max_levels=1, reps=10, use_cache=False)
+        xr = inputs.device_uniform_complex(n * B, args.seed + 6, torch.complex64, dev)
+        yr = torch.empty_like(xr)
+        rec = {"n": n, "batch": B}
+        for name, lift, tuning in (("radix16", None, None), ("tuned", best["lift"], best["tuning"])):
+            p = mfft.Plan(n, B, lift, tuning=tuning)
+            for _ in range(3):
+                p.forward(xr, out=yr)
+            ms = time_events(lambda: p.forward(xr, out=yr), reps, torch)
+            rec[name] = {"ms": round(ms, 5), "gflops": round(gflops(n, B, ms * 1e-3), 1),
+                         "frac_hbm_peak": round(16 * n * B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "stage_lg_radices": [q["stage_lg_radices"] for q in p.describe()["passes"]],
+                         "tuning": tuning}
+            samples.setdefault("radix_" + name, []).append(
+                (xr.view(B, n)[0].cpu().numpy(), yr.view(B, n)[0].cpu().numpy(), 2e-6 * 14))
+            p.close()
+        rec["tuned_vs_radix16"] = round(rec["radix16"]["ms"] / rec["tuned"]["ms"], 3)
+        ex["radix_tuned_b1024_2^14"] = rec
+        del xr, yr
 
     if want("nd"):
         # Multi-dimensional transforms of 2^24 complex64 points: 4096 x 4096

@@ -119,7 +119,21 @@ typedef struct {
                                    0 = when the input is at most 256 MiB
                                    (the Infinity Cache), 1 = always,
                                    -1 = never; other values MOA_ERR_TUNING  */
-    int32_t reserved[6];
+    uint32_t lg_radix;          /* largest register radix of each level's
+                                   stages, 4 bits per level (level l in
+                                   bits 4l .. 4l+3): log2 of the radix, 0 =
+                                   the default (16, i.e. 4), 2 / 3 / 5 =
+                                   radix 4 / 8 / 32 (the general-radix
+                                   block of Ch. 1, Fig. radnbutterfly):
+                                   stages of that radix, then one with the
+                                   remaining radix.  Other radices run the
+                                   level kernel (complex64 levels of 2^5 ..
+                                   2^14 points, not the split precisions);
+                                   radix 32 needs 32 points a thread,
+                                   i.e. a level that stores in its load
+                                   pattern, with at most 512 threads.
+                                   Anything else MOA_ERR_TUNING            */
+    int32_t reserved[5];
 } moa_fft_tuning_t;
 
 /*

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmoa_fft.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "fft_kernels.hip", "fft_pair.hip", "fft_small.hip", "fft_batched.hip", "fft_mfma.hip",
+SOURCES = ["plan.cpp", "fft_kernels.hip", "fft_radix.hip", "fft_pair.hip", "fft_small.hip", "fft_batched.hip", "fft_mfma.hip",
            "scratch.hip", "hypercube.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

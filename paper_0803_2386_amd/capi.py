@@ -54,7 +54,8 @@ class moa_fft_tuning_t(ctypes.Structure):
     _fields_ = [("cols_per_block", ctypes.c_int32 * 8),
                 ("persistent_blocks", ctypes.c_int32),
                 ("stream", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("lg_radix", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class MoaError(RuntimeError):
@@ -128,6 +129,11 @@ def _tuning(tuning):
         t.cols_per_block[i] = int(v)
     t.persistent_blocks = int(tuning.get("persistent_blocks", 0))
     t.stream = int(tuning.get("stream", 0))
+    # lg_radix: a list, one log2 radix per level (0 = default), packed 4 bits a level
+    packed = 0
+    for i, v in enumerate(tuning.get("lg_radix", [])[:8]):
+        packed |= (int(v) & 0xF) << (4 * i)
+    t.lg_radix = packed
     return ctypes.pointer(t)
 
 

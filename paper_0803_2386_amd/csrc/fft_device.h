@@ -219,23 +219,24 @@ __device__ __forceinline__ void dft_dir(V* v)
     }
 }
 
-// Stage schedule of a length-2^lgn transform: radix-16 stages, then one stage
-// with the remaining radix.  A thread holds 2^lge points (16 or 32), i.e.
-// NB = 2^lge / radix butterflies of each stage.
+// Stage schedule of a length-2^lgn transform: stages of radix 2^lgrad (the
+// general-radix block of Ch. 1, Fig. radnbutterfly; 16 by default), then one
+// stage with the remaining radix.  A thread holds 2^lge points (16 or 32),
+// i.e. NB = 2^lge / radix butterflies of each stage, so lgrad <= lge.
 constexpr int kLgRadix = 4;
 __host__ __device__ constexpr int lg_e(int lgn, int lge) { return lgn < lge ? lgn : lge; }
-__host__ __device__ constexpr int n_stages(int lgn)
+__host__ __device__ constexpr int n_stages(int lgn, int lgrad = kLgRadix)
 {
-    return lgn <= kLgRadix ? 1 : lgn / kLgRadix + ((lgn % kLgRadix) ? 1 : 0);
+    return lgn <= lgrad ? 1 : lgn / lgrad + ((lgn % lgrad) ? 1 : 0);
 }
-__host__ __device__ constexpr int stage_lgr(int lgn, int s)
+__host__ __device__ constexpr int stage_lgr(int lgn, int s, int lgrad = kLgRadix)
 {
-    return lgn <= kLgRadix ? lgn : (s < lgn / kLgRadix ? kLgRadix : lgn % kLgRadix);
+    return lgn <= lgrad ? lgn : (s < lgn / lgrad ? lgrad : lgn % lgrad);
 }
-__host__ __device__ constexpr int stage_lgns(int lgn, int s)
+__host__ __device__ constexpr int stage_lgns(int lgn, int s, int lgrad = kLgRadix)
 {
     int acc = 0;
-    for (int i = 0; i < s; ++i) acc += stage_lgr(lgn, i);
+    for (int i = 0; i < s; ++i) acc += stage_lgr(lgn, i, lgrad);
     return acc;
 }
 
@@ -308,12 +309,13 @@ __device__ __forceinline__ void store_once(double2* p, double2 v)
     __builtin_nontemporal_store((v2){v.x, v.y}, reinterpret_cast<v2*>(p));
 }
 
-template <int LGN, int LGE, int S>
+template <int LGN, int LGE, int S, int LGRAD = kLgRadix>
 struct StageTw {
+    static_assert(LGRAD <= LGE || LGN <= LGE, "a stage's radix must fit the points of a thread");
     static constexpr int N = 1 << LGN;
-    static constexpr int LGR = stage_lgr(LGN, S);
+    static constexpr int LGR = stage_lgr(LGN, S, LGRAD);
     static constexpr int RS = 1 << LGR;
-    static constexpr int LGNS = stage_lgns(LGN, S);
+    static constexpr int LGNS = stage_lgns(LGN, S, LGRAD);
     static constexpr int NS = 1 << LGNS;
     static constexpr int E = 1 << lg_e(LGN, LGE);
     static constexpr int TPC = N / E;
@@ -322,10 +324,10 @@ struct StageTw {
 
 // Register slot of the point j + m*TPC a thread loads before stage 0: input r
 // of butterfly q sits in slot q*RS + r and is point j + (q + r*NB)*TPC.
-template <int LGN, int LGE>
+template <int LGN, int LGE, int LGRAD = kLgRadix>
 __host__ __device__ constexpr int in_slot(int m)
 {
-    using I = StageTw<LGN, LGE, 0>;
+    using I = StageTw<LGN, LGE, 0, LGRAD>;
     return (m % I::NB) * I::RS + m / I::NB;
 }
 
@@ -335,11 +337,11 @@ __host__ __device__ constexpr int in_slot(int m)
 // the powers of its set bits in turn (at most five roundings).
 constexpr int kMaxStageTw = 16;
 
-template <typename R, int LGN, int LGE, int S, typename V>
+template <typename R, int LGN, int LGE, int S, int LGRAD = kLgRadix, typename V>
 __device__ __forceinline__ void load_stage_twiddles(V (&tw)[kMaxStageTw], int j, R sign, const V* tl)
 {
-    using I = StageTw<LGN, LGE, S>;
-    if constexpr (S < n_stages(LGN) && I::NS > 1) {
+    using I = StageTw<LGN, LGE, S, LGRAD>;
+    if constexpr (S < n_stages(LGN, LGRAD) && I::NS > 1) {
         static_assert(I::NB * I::LGR <= kMaxStageTw, "stage twiddle buffer too small");
 #pragma unroll
         for (int q = 0; q < I::NB; ++q) {
@@ -365,13 +367,13 @@ __device__ __forceinline__ void load_stage_twiddles(V (&tw)[kMaxStageTw], int j,
 // holds the stage's twiddle powers, read one stage ahead from the LDS table
 // `twb` (see tw_blk).  Threads with active == false only take part in the
 // barriers.
-template <typename R, int LGN, int LGE, int S, bool FROM_LDS, typename V>
+template <typename R, int LGN, int LGE, int S, bool FROM_LDS, int LGRAD = kLgRadix, typename V>
 __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V* twb, bool active,
                                            V (&tw)[kMaxStageTw])
 {
-    constexpr int NST = n_stages(LGN);
+    constexpr int NST = n_stages(LGN, LGRAD);
     if constexpr (S < NST) {
-        using I = StageTw<LGN, LGE, S>;
+        using I = StageTw<LGN, LGE, S, LGRAD>;
         constexpr int N = I::N, LGR = I::LGR, RS = I::RS, LGNS = I::LGNS, NS = I::NS, TPC = I::TPC, NB = I::NB;
         constexpr bool READS_LDS = (S > 0) || FROM_LDS;
         if constexpr (READS_LDS) {
@@ -405,7 +407,7 @@ __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V*
             // stored just before the stages (a batched task stores it with
             // its data loads in flight).
             if constexpr (READS_LDS) {
-                if (active) load_stage_twiddles<R, LGN, LGE, S + 1>(tw, j, sign, twb);
+                if (active) load_stage_twiddles<R, LGN, LGE, S + 1, LGRAD>(tw, j, sign, twb);
                 __syncthreads();
             }
             if (active) {
@@ -419,9 +421,9 @@ __device__ __forceinline__ void run_stages(V* v, V* col, int j, R sign, const V*
             }
             __syncthreads();
             if constexpr (!READS_LDS) {
-                if (active) load_stage_twiddles<R, LGN, LGE, S + 1>(tw, j, sign, twb);
+                if (active) load_stage_twiddles<R, LGN, LGE, S + 1, LGRAD>(tw, j, sign, twb);
             }
-            run_stages<R, LGN, LGE, S + 1, FROM_LDS>(v, col, j, sign, twb, active, tw);
+            run_stages<R, LGN, LGE, S + 1, FROM_LDS, LGRAD>(v, col, j, sign, twb, active, tw);
         }
     }
 }
@@ -520,10 +522,10 @@ __device__ __forceinline__ void pair_stages(float2* v0, float2* v1, float2* col,
 
 // Position, in units of TPC past the thread's row j, of the output element
 // held in register slot m after the last stage.
-template <int LGN, int LGE>
+template <int LGN, int LGE, int LGRAD = kLgRadix>
 __host__ __device__ constexpr int out_slot_rank(int m)
 {
-    using I = StageTw<LGN, LGE, n_stages(LGN) - 1>;
+    using I = StageTw<LGN, LGE, n_stages(LGN, LGRAD) - 1, LGRAD>;
     return m / I::RS + (m % I::RS) * I::NB;
 }
 

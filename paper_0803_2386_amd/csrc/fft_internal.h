@@ -12,6 +12,7 @@ namespace moa {
 
 constexpr int kMaxDigits = 8;     // batch digits of one pass descriptor
 constexpr int kMaxPasses = 8;     // passes of one plan (lift rank or array rank <= 8)
+constexpr int kLgRadixDefault = 4;  // register stages of radix 16 unless tuned otherwise
 constexpr int kMaxThreads = 512;  // level-kernel workgroup limit (1024: staged-store, paired-column and batch kernels)
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kNoBlock = 30;      // lgb of an axis with one plain stride
@@ -101,6 +102,7 @@ struct PassDesc {
     int xcd_remap = 0;
     int mfma = 0;                 // 0 = VALU radix-16, 1 = split bf16 MFMA, 2 = split fp16 MFMA
     int pre_lg = 0;               // log2 of the points transformed by earlier levels
+    int lgrad = 0;                // log2 of the largest register radix of the level kernel (0: 16)
     // Blocked layouts (paired-column kernel only).  Row k of the DFT axis
     // lies at (k mod 2^lgb) * s_e + (k >> lgb) * s_hi (lgb = kNoBlock: k * s_e);
     // column w of tile t of digit 0 at t * tile_s + (w / 2) * pair_s +
@@ -190,6 +192,10 @@ const void* small_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
 // through the plan's graphs) with `ws` as the workspace.
 moa_status_t check_exec(moa_fft_plan_t p, int dir, const void* in, const void* out, size_t* ws_bytes);
 moa_status_t launch_on_workspace(moa_fft_plan_t p, int dir, const void* in, void* out, void* ws, hipStream_t s);
+// The level kernel with register stages of radix 2^d.lgrad (fft_radix.hip;
+// lgrad 2, 3 or 5, complex64 levels of 2^5 .. 2^14 points); nullptr where no
+// such kernel exists.
+const void* radix_pass_fn(const PassDesc& d);
 // The kernel function pointers, used to build HIP graph nodes.
 const void* pass_kernel_fn(bool fp64, const PassDesc& d, bool fwd);
 const void* batched_kernel_fn(bool fp64, bool fwd);

@@ -133,6 +133,13 @@ int lgE(int lgn, int lge) { return lgn < lge ? lgn : lge; }
 moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
 {
     const int lgn = d.lgn;
+    // A register radix other than 16 runs the level kernel's other-radix
+    // instantiations: complex64, 2^5 .. 2^14 points, radix 4, 8 or 32.
+    if (d.lgrad == moa::kLgRadixDefault) d.lgrad = 0;
+    const bool other_radix = d.lgrad != 0;
+    if (other_radix && (fp64 || d.mfma || lgn < 5 || lgn > moa::kMaxLgBlockC64 ||
+                        (d.lgrad != 2 && d.lgrad != 3 && d.lgrad != 5)))
+        return MOA_ERR_TUNING;
     const int maxT = max_threads(fp64);
     // Points per thread: 16, or 32 when 16 would need more than maxT threads
     // (complex64 only); the matrix-core kernel always holds 32.
@@ -144,15 +151,18 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     // up to 1024 threads (mode 2).
     auto big = [&](int lgw) { return ((int64_t(1) << (lgn + lgw)) >> 4) > maxT; };
     auto kmode_for = [&](int lgw) {
-        if (d.mfma || fp64 || !big(lgw)) return 0;
         const bool tf = lgw > 0;
+        // Radix 32 needs 32 points a thread: mode 1 (a level that stores in
+        // its load pattern).
+        if (d.lgrad == 5) return ((tf && in_tf) == (tf && out_tf)) ? 1 : -1;
+        if (d.mfma || fp64 || !big(lgw)) return 0;
         return ((tf && in_tf) == (tf && out_tf)) ? 1 : 2;
     };
     auto lge_for = [&](int lgw) {
         if (d.mfma) return 5;
         return kmode_for(lgw) == 1 ? 5 : 4;
     };
-    auto maxT_for = [&](int lgw) { return kmode_for(lgw) == 2 ? 1024 : maxT; };
+    auto maxT_for = [&](int lgw) { return kmode_for(lgw) == 2 ? 1024 : (kmode_for(lgw) < 0 ? 0 : maxT); };
     auto tpc_for = [&](int lgw) { return 1 << (lgn - lgE(lgn, lge_for(lgw))); };
     const int min_lgw = d.mfma ? std::max(0, 11 - lgn) : 0;
     // A lone digit 0 may have any size: its tiles must divide it.
@@ -202,7 +212,8 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     // the latency kernel (fft_small.hip) spreads it over N / 4 threads of 4
     // points, radix-4 stages.  A small batch of them runs one such workgroup
     // per transform.
-    if (want_w <= 0 && !d.mfma && !d.tw && d.pre_lg == 0 && d.nd == 1 && d.size[0] <= moa::kSmallMaxBatch &&
+    if (want_w <= 0 && !other_radix && !d.mfma && !d.tw && d.pre_lg == 0 && d.nd == 1 &&
+        d.size[0] <= moa::kSmallMaxBatch &&
         (d.size[0] << lgn) <= (int64_t(1) << moa::kLgSmallMaxPoints) &&
         d.in_s_e == 1 && d.out_s_k == 1 && d.in_s[0] == (int64_t(1) << lgn) && d.out_s[0] == (int64_t(1) << lgn) &&
         lgn >= moa::kLgSmallMin && lgn <= (fp64 ? moa::kLgSmallMaxC128 : moa::kLgSmallMax)) {
@@ -241,7 +252,7 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         d.xcd_remap = (blocks % 8 == 0 && blocks >= 16) ? 1 : 0;
         return MOA_OK;
     };
-    if (want_w > 0 ? (is_pow2(want_w) && pair_ok(lg2(want_w))) : pair_ok(15 - lgn))
+    if (!other_radix && (want_w > 0 ? (is_pow2(want_w) && pair_ok(lg2(want_w))) : pair_ok(15 - lgn)))
         return finish_pair(want_w > 0 ? lg2(want_w) : 15 - lgn);
     int lgw = 0;
     if (want_w > 0) {
@@ -267,6 +278,7 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     d.lgw = lgw;
     d.lge = lge_for(lgw);
     d.kmode = kmode_for(lgw);
+    if (d.kmode < 0) return MOA_ERR_TUNING;  // radix 32 on a level whose store changes the thread map
     d.in_tile_fast = lgw > 0 && in_tf;
     d.out_tile_fast = lgw > 0 && out_tf;
     const auto cl = lds_for(lgw, d.in_tile_fast);
@@ -391,6 +403,7 @@ moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         if (p->prec != MOA_FFT_PREC_NATIVE && d.lgn % 4 == 0 && d.lgn >= 4 && d.lgn <= 12) d.mfma = p->prec;
         const int want = tuning ? tuning->cols_per_block[l] : 0;
         if (tuning && (want < 0)) return MOA_ERR_TUNING;
+        d.lgrad = tuning ? int((tuning->lg_radix >> (4 * l)) & 0xFu) : 0;
         moa_status_t st = finish_pass(d, p->fp64, want, p->cus);
         if (st != MOA_OK) return st;
         // The level kernel applies the inter-level factor only when it stores
@@ -444,6 +457,7 @@ moa_status_t lower_nd(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         const int l = int(p->passes.size());
         const int want = tuning ? tuning->cols_per_block[l] : 0;
         if (want < 0) return MOA_ERR_TUNING;
+        d.lgrad = tuning ? int((tuning->lg_radix >> (4 * l)) & 0xFu) : 0;
         moa_status_t st = finish_pass(d, p->fp64, want, p->cus);
         if (st != MOA_OK) return st;
         p->passes.push_back(d);
@@ -597,6 +611,31 @@ moa_status_t finalize(moa_fft_plan_s* p, moa_fft_plan_t* out)
 // ---------------------------------------------------------------------------
 // JSON description
 // ---------------------------------------------------------------------------
+
+// log2 radices of a level's stages: the short-transform kernel runs radix-4
+// stages (one radix-2 stage when log2 N is odd); the others stages of the
+// level's largest radix, then one with the remaining radix.
+std::string stage_radices(const PassDesc& d)
+{
+    std::string out = "[";
+    auto add = [&](int r) {
+        if (out.size() > 1) out += ",";
+        out += std::to_string(r);
+    };
+    if (d.kmode == 4) {
+        for (int left = d.lgn; left > 0; left -= std::min(2, left)) add(std::min(2, left));
+    } else {
+        const int g = d.lgrad ? d.lgrad : moa::kLgRadixDefault;
+        if (d.lgn <= g) {
+            if (d.lgn > 0) add(d.lgn);
+        } else {
+            for (int i = 0; i < d.lgn / g; ++i) add(g);
+            if (d.lgn % g) add(d.lgn % g);
+        }
+    }
+    return out + "]";
+}
+
 std::string describe_json(const moa_fft_plan_s* p)
 {
     std::string s;
@@ -640,12 +679,13 @@ std::string describe_json(const moa_fft_plan_s* p)
             (long long)(d.out_tile_s ? d.out_tile_s : (int64_t(1) << d.lgw) * d.out_s[0]));
         add("},\"twiddle_root\":%lld,\"twiddle_parts\":%d,\"grid\":%lld,\"tile_width\":%d,\"threads\":%d,\"blocks\":%lld,\"lds_bytes\":%d,"
             "\"lds_col_stride\":%d,\"in_tile_fast\":%s,\"out_tile_fast\":%s,\"xcd_remap\":%d,\"mfma\":\"%s\","
-            "\"points_per_thread\":%d,\"kernel_mode\":%d}",
+            "\"points_per_thread\":%d,\"kernel_mode\":%d,\"lg_radix\":%d,\"stage_lg_radices\":%s}",
             d.tw ? (long long)(int64_t(1) << d.tw_lgroot) : 0LL, d.tw ? d.tw_parts : 0, (long long)d.grid, 1 << d.lgw,
             d.threads, (long long)d.blocks,
             d.lds_bytes, d.col_stride, d.in_tile_fast ? "true" : "false", d.out_tile_fast ? "true" : "false",
             d.xcd_remap, d.mfma == 0 ? "none" : (d.mfma == 1 ? "split_bf16" : "split_fp16"),
-            (d.mfma || d.kmode == 3) ? 32 : (1 << lgE(d.lgn, d.lge)), d.kmode);
+            (d.mfma || d.kmode == 3) ? 32 : (1 << lgE(d.lgn, d.lge)), d.kmode,
+            d.kmode == 4 ? 2 : (d.lgrad ? d.lgrad : moa::kLgRadixDefault), stage_radices(d).c_str());
     }
     s += "]";
     if (p->batched) {

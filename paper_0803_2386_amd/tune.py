@@ -1,9 +1,12 @@
-"""Autotuner: picks the lift and the per-level tile widths of a plan by timing
-candidates on the device, and the grid of an uneven batch's fused launch.
+"""Autotuner: picks the lift, the per-level tile widths and the per-level
+register radix of a plan by timing candidates on the device, and the grid
+and streaming mode of an uneven batch's fused launch.
 
 The paper leaves the blocking size c as a run-time parameter to be chosen per
 machine (Ch. 1 and Ch. 3, "Results and Discussion": the best c was found by
-experiment, not from the cache size).  Here the candidates are lifts whose
+experiment, not from the cache size), and so is the radix of the butterflies
+(Ch. 1, "Performance of the General-Radix FFT", Table 4: the best radix was
+measured, not derived).  Here the candidates are lifts whose
 levels each fit one workgroup, in the paper's uniform form
 <2^p_max c ... c> and in balanced mixed forms, each with a few tile widths;
 every candidate is planned through the C ABI, timed with HIP events, and the
@@ -65,12 +68,36 @@ def library_digest() -> str:
 
 
 def _key(device_name: str, dtype_code: int, n: int, batch: int, prec: int, max_levels: int = 3,
-         limit: Optional[int] = None, refine: int = 5) -> str:
+         limit: Optional[int] = None, refine: int = 5, radix: bool = True) -> str:
     """Cache key: the problem, the search that answered it (a search cut
     short by a candidate limit is not the answer of a full one) and the
     library it timed."""
     return (f"{device_name}|{'c64' if dtype_code == capi.MOA_C64 else 'c128'}|p{prec}|n{n}|b{batch}"
-            f"|L{max_levels}|lim{limit or 0}|r{refine}|lib{library_digest()}")
+            f"|L{max_levels}|lim{limit or 0}|r{refine}|rad{int(radix)}|lib{library_digest()}")
+
+
+RADIX_CHOICES = (2, 3, 5)   # log2 of radix 4, 8, 32 (0 = the default radix 16)
+
+
+def radix_candidates(n: int, batch: int, lift: Sequence[int], tuning: Optional[dict], dtype_code: int,
+                     prec: int) -> List[dict]:
+    """Tunings that change one level's register radix of (lift, tuning),
+    keeping everything else; only those that plan."""
+    base = dict(tuning or {})
+    L = len(lift)
+    cur = list(base.get("lg_radix", [0] * L))
+    out = []
+    for lvl in range(L):
+        for g in RADIX_CHOICES:
+            if cur[lvl] == g:
+                continue
+            t = dict(base)
+            lr = list(cur)
+            lr[lvl] = g
+            t["lg_radix"] = lr
+            if _plan_ok(n, batch, lift, dtype_code, prec, t) is not None:
+                out.append(t)
+    return out
 
 
 def lift_candidates(n: int, dtype_code: int = capi.MOA_C64, max_levels: int = 3) -> List[List[int]]:
@@ -145,12 +172,14 @@ def _time_plan(torch, plan, x, out, reps: int) -> float:
 
 def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: int = 3, reps: int = 10,
          candidates_limit: Optional[int] = None, use_cache: bool = True, verbose: bool = False,
-         refine: int = 5) -> dict:
-    """Time the candidate lifts/tile widths for (n, batch) on the current
-    device; returns {"lift", "tuning", "ms", "tried"} and caches it.
+         refine: int = 5, radix: bool = True) -> dict:
+    """Time the candidate lifts/tile widths/radices for (n, batch) on the
+    current device; returns {"lift", "tuning", "ms", "tried"} and caches it.
 
-    Two rounds: every lift with the planner's default tile widths, then every
-    tile width for the `refine` fastest lifts."""
+    Rounds: every lift with the planner's defaults; every tile width for the
+    `refine` fastest lifts; then (radix=True) for the three fastest so far,
+    each level's register radix changed one level at a time, and the best
+    change of every level combined."""
     import torch
 
     from . import fft as mfft
@@ -159,7 +188,7 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
     pcode = mfft._PREC[prec]
     dev = torch.device("cuda", torch.cuda.current_device())
     name = torch.cuda.get_device_name(dev)
-    key = _key(name, dcode, n, batch, pcode, max_levels, candidates_limit, refine)
+    key = _key(name, dcode, n, batch, pcode, max_levels, candidates_limit, refine, radix)
     if use_cache:
         with _lock:
             hit = _load_cache().get(key)
@@ -186,6 +215,28 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
     for r in top:
         run([c for c in candidates(n, batch, dcode, pcode, max_levels=len(r["lift"]))
              if c[0] == r["lift"] and c[1] is not None])
+    if radix:
+        for r in sorted(timed, key=lambda r: r["ms"])[:3]:
+            lift, tuning = r["lift"], r["tuning"]
+            before = len(timed)
+            run([(lift, t) for t in radix_candidates(n, batch, lift, tuning, dcode, pcode)])
+            trial = [q for q in timed[before:]]
+            # combine the best radix of each level when several levels gained
+            per_level = {}
+            for q in trial:
+                lr = q["tuning"]["lg_radix"]
+                base_lr = (tuning or {}).get("lg_radix", [0] * len(lift))
+                lvl = next(i for i in range(len(lift)) if lr[i] != base_lr[i])
+                if q["ms"] < r["ms"] and (lvl not in per_level or q["ms"] < per_level[lvl]["ms"]):
+                    per_level[lvl] = q
+            if len(per_level) > 1:
+                t = dict(tuning or {})
+                lr = list(t.get("lg_radix", [0] * len(lift)))
+                for lvl, q in per_level.items():
+                    lr[lvl] = q["tuning"]["lg_radix"][lvl]
+                t["lg_radix"] = lr
+                if _plan_ok(n, batch, lift, dcode, pcode, t) is not None:
+                    run([(lift, t)])
     best = dict(min(timed, key=lambda r: r["ms"]))
     best["tried"] = len(timed)
     if use_cache:
@@ -197,10 +248,11 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
 
 
 def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 256, 512, 768, 1024, 1536, 2048),
-                 reps: int = 10, verbose: bool = False) -> dict:
+                 reps: int = 10, verbose: bool = False, streams: Iterable[int] = (0, 1, -1)) -> dict:
     """Time grids of an uneven batch's fused launch (0 = one workgroup per
-    task, the default; smaller grids make it persistent); returns the best
-    tuning."""
+    task, the default; smaller grids make it persistent), then the streaming
+    modes of its loads and stores (0 = by size, 1 = always, -1 = never) at the
+    best grid; returns the best tuning."""
     import torch
 
     from . import fft as mfft
@@ -220,6 +272,18 @@ def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 25
             print(f"tune batched grid={grid}: {ms:.4f} ms", flush=True)
         if best is None or ms < best["ms"]:
             best = {"tuning": tuning, "grid": grid, "ms": ms}
+    for sm in streams:
+        if sm == 0:
+            continue
+        tuning = dict(best["tuning"] or {})
+        tuning["stream"] = int(sm)
+        plan = mfft.BatchedPlan(sizes, dtype=dtype, tuning=tuning)
+        ms = _time_plan(torch, plan, x, out, reps)
+        plan.close()
+        if verbose:
+            print(f"tune batched grid={best['grid']} stream={sm}: {ms:.4f} ms", flush=True)
+        if ms < best["ms"]:
+            best = {"tuning": tuning, "grid": best["grid"], "ms": ms}
     return best
 
 

@@ -527,3 +527,43 @@ def test_block_diagonal_transpose_vector_is_the_inverse_of_the_printed_one():
     for n, gated in [(4, [0, 2]), (4, [1, 2]), (6, [5, 0, 3]), (3, [0])]:
         printed = moa.gate_transpose_vector(n, gated)
         assert hypercube.block_diagonal_transpose_vector(n, gated) == moa.inverse_permutation(printed)
+
+
+@pytest.mark.parametrize("n,lift,dtype,prec,lg_radix,want", [
+    (1 << 16, [256, 256], capi.MOA_C64, 0, [3, 2], capi.MOA_OK),
+    (1 << 16, [256, 256], capi.MOA_C64, 0, [5, 0], capi.MOA_OK),
+    (1 << 20, None, capi.MOA_C64, 0, [5, 5], capi.MOA_OK),
+    (1 << 14, None, capi.MOA_C64, 0, [2], capi.MOA_OK),
+    (1 << 16, [256, 256], capi.MOA_C128, 0, [3, 0], capi.MOA_ERR_TUNING),     # complex128: radix 16 only
+    (1 << 16, [256, 256], capi.MOA_C64, 2, [3, 0], capi.MOA_ERR_TUNING),      # split precision
+    (1 << 8, [16, 16], capi.MOA_C64, 0, [2, 0], capi.MOA_ERR_TUNING),         # a level below 2^5 points
+    (1 << 16, [256, 256], capi.MOA_C64, 0, [1, 0], capi.MOA_ERR_TUNING),      # radix 2 is not offered
+    (1 << 16, [256, 256], capi.MOA_C64, 0, [6, 0], capi.MOA_ERR_TUNING),
+    (1 << 16, [256, 256], capi.MOA_C64, 0, [4, 4], capi.MOA_OK),              # 4 = the default
+])
+def test_radix_tuning_validation(n, lift, dtype, prec, lg_radix, want):
+    st = status_of(capi.moa_fft_plan, n, 1, lift, dtype=dtype, prec=prec, flags=HOST,
+                   tuning={"lg_radix": lg_radix})
+    assert st == want
+
+
+def test_radix_schedule_in_describe():
+    h = capi.moa_fft_plan(1 << 16, 2, [256, 256], flags=HOST, tuning={"lg_radix": [3, 5]})
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+        p0, p1 = d["passes"]
+        assert p0["lg_radix"] == 3 and p0["stage_lg_radices"] == [3, 3, 2]
+        assert p1["lg_radix"] == 5 and p1["stage_lg_radices"] == [5, 3] and p1["points_per_thread"] == 32
+        assert p1["kernel_mode"] == 1
+    finally:
+        capi.moa_fft_destroy(h)
+    h = capi.moa_fft_plan(1 << 24, 1, [4096, 4096], flags=HOST)
+    try:
+        assert [p["stage_lg_radices"] for p in json.loads(capi.moa_fft_describe(h))["passes"]] == [[4, 4, 4]] * 2
+    finally:
+        capi.moa_fft_destroy(h)
+    h = capi.moa_fft_plan(1 << 10, 1, None, flags=HOST)   # the short-transform kernel: radix 4
+    try:
+        assert json.loads(capi.moa_fft_describe(h))["passes"][0]["stage_lg_radices"] == [2] * 5
+    finally:
+        capi.moa_fft_destroy(h)

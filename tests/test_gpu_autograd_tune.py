@@ -105,3 +105,20 @@ def test_tuner_picks_a_correct_plan(tmp_path, monkeypatch):
     assert err <= 2e-6 * 16
     g = tune.tune_batched([64, 4096, 16384, 512] * 20, grids=(0, 64), reps=2)
     assert g["ms"] > 0
+
+
+def test_tuner_radix_round_picks_a_correct_plan(tmp_path, monkeypatch):
+    """The radix round of the tuner (register radix 4 / 8 / 32 per level)
+    on 64 transforms of 2^14 points; whatever it picks matches the oracle."""
+    need_gpu()
+    monkeypatch.setenv("MOA_FFT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    n, B = 1 << 14, 64
+    best = tune.tune(n, B, max_levels=1, reps=3, refine=1, verbose=True)
+    assert best["tried"] >= 4
+    plan = mfft.Plan(n, B, best["lift"], tuning=best["tuning"])
+    x = inputs.uniform_complex((B, n), 6, np.complex64)
+    got = plan.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.complex128)
+    want = oracle.fft(x.astype(np.complex128))
+    err = float((np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)).max())
+    print(f"tuned 64 x 2^14: {best['tuning']} {best['ms']:.4f} ms, err {err:.3e}", flush=True)
+    assert err <= 2e-6 * 14

@@ -36,3 +36,15 @@ def test_cache_key_names_the_search_and_the_library():
     k_deep = tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 4, None, 5)
     assert len({k_full, k_cut, k_deep}) == 3
     assert tune.library_digest() in k_full
+
+
+def test_radix_candidates_change_one_level_and_plan():
+    cands = tune.radix_candidates(1 << 16, 4, [256, 256], None, capi.MOA_C64, 0)
+    assert cands, "no radix candidates"
+    for t in cands:
+        lr = t["lg_radix"]
+        assert sum(1 for v in lr if v) == 1 and set(lr) <= {0, 2, 3, 5}
+    # complex128 levels keep radix 16: no candidates
+    assert tune.radix_candidates(1 << 16, 4, [256, 256], None, capi.MOA_C128, 0) == []
+    k = tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 3, None, 5, radix=False)
+    assert k != tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 3, None, 5, radix=True)
