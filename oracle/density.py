@@ -89,3 +89,15 @@ def moa_source_offsets_fast(m: int, t: Sequence[int]) -> np.ndarray:
         bit = (i >> (m - 1 - int(t[k]))) & 1
         src |= bit << (m - 1 - k)
     return src
+
+
+def hypercube_source_of(m: int, t, offsets) -> np.ndarray:
+    """gamma(i[t]; <2 ... 2>) for the result offsets given (any subset of the
+    2^m), by the same bit rule as moa_source_offsets_fast: for large arrays
+    whose full offset table would not fit the host."""
+    m = int(m)
+    i = np.asarray(offsets, dtype=np.int64)
+    src = np.zeros_like(i)
+    for k in range(m):
+        src |= ((i >> (m - 1 - int(t[k]))) & 1) << (m - 1 - k)
+    return src

@@ -156,3 +156,59 @@ def test_large_gate_sampled_blocks():
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
     print(f"gate n=13 rel err {err:.3e}", flush=True)
     assert err <= gate_tol(2, torch.complex64)
+
+
+def test_transpose_largest_arrays():
+    """Rank 30 with 8-byte elements (8 GiB each way) and rank 31 with 4-byte
+    elements (every element distinct): the inverse permutation restores the input exactly, and 4096
+    seeded output positions hold the input element the normal form names."""
+    need_gpu()
+    rng = np.random.default_rng(30)
+    for m, dtype in ((30, torch.complex64), (31, torch.int32)):
+        t = [int(v) for v in rng.permutation(m)]
+        inv = moa.inverse_permutation(t)
+        if dtype == torch.int32:
+            x = torch.arange(1 << m, dtype=torch.int32, device="cuda")   # every value distinct
+        else:
+            i = torch.arange(1 << m, dtype=torch.int64, device="cuda")
+            x = torch.complex((i >> 15).to(torch.float32), (i & 32767).to(torch.float32))  # distinct, exact
+            del i
+        y = hc.hypercube_transpose(x, t)
+        idx = rng.integers(0, 1 << m, 4096)
+        src = density.hypercube_source_of(m, t, idx)
+        got = y[torch.from_numpy(idx).cuda()].cpu().numpy()
+        want = x[torch.from_numpy(src).cuda()].cpu().numpy()
+        assert np.array_equal(got, want), (m, dtype)
+        z = hc.hypercube_transpose(y, inv)
+        torch.cuda.synchronize()
+        assert torch.equal(z, x), (m, dtype)
+        print(f"transpose rank {m} {dtype}: round trip exact, 4096 positions exact", flush=True)
+        del x, y, z
+        torch.cuda.empty_cache()
+
+
+def test_gate_largest_matrix_sampled_blocks():
+    """15 qubits (2^30 complex64 elements, 8 GiB), gated qubits 0 and 14:
+    256 seeded blocks of the block-diagonal view read back before and after
+    the gate, each checked against U B U^H in FP64."""
+    need_gpu()
+    n, gated = 15, [0, 14]
+    N = 1 << n
+    rng = np.random.default_rng(15)
+    U = rand_unitary(4, rng).astype(np.complex64)
+    rho = torch.randn(N * N, dtype=torch.complex64, device="cuda")
+    # element addresses of 256 blocks: free bits random, gated bits enumerated
+    free_mask = (N - 1) & ~((1 << 0) | (1 << 14))
+    rows = rng.integers(0, N, 256) & free_mask
+    cols = rng.integers(0, N, 256) & free_mask
+    ab = np.array([(a >> 1) << 14 | (a & 1) for a in range(4)])   # U index bit 1 = qubit 14, bit 0 = qubit 0
+    addr = (rows[:, None, None] | ab[None, :, None]) * N + (cols[:, None, None] | ab[None, None, :])
+    at = torch.from_numpy(addr.reshape(-1)).cuda()
+    before = rho[at].cpu().numpy().astype(np.complex128).reshape(256, 4, 4)
+    hc.density_gate(rho.view(N, N), torch.from_numpy(U).cuda(), gated)
+    after = rho[at].cpu().numpy().astype(np.complex128).reshape(256, 4, 4)
+    Ud = U.astype(np.complex128)
+    want = np.einsum("ak,rkl,bl->rab", Ud, before, Ud.conj())
+    err = np.linalg.norm(after - want) / np.linalg.norm(want)
+    print(f"gate 15 qubits, 256 blocks: rel err {err:.3e}", flush=True)
+    assert err <= gate_tol(2, torch.complex64)

@@ -135,3 +135,39 @@ def test_nd_misaligned_output_is_rejected():
         capi.moa_fft_exec(plan._h, 0, x.data_ptr(), odd.data_ptr(), 0)
     assert e.value.status == capi.MOA_ERR_ARG
     plan.close()
+
+
+def test_nd_largest_array_plane_wave_and_round_trip():
+    """16384 x 16384 x 4 complex64 (2^30 points, 8 GiB): a plane wave goes to
+    N delta at its frequency, and the adjoint of the transform of seeded data
+    returns N x (properties exact at any size; tolerance the FP32 bound of
+    the transform, twice for the round trip)."""
+    need_gpu()
+    dims = (16384, 16384, 4)
+    N = int(np.prod(dims))
+    k0 = (123, 16000, 3)
+    plan = mfft.NDPlan(dims, 1)
+    # plane wave exp(2 pi i sum_a j_a k0_a / n_a), built in float64 on the device
+    ph = torch.zeros(dims, dtype=torch.float64, device="cuda")
+    for ax, (n_a, k_a) in enumerate(zip(dims, k0)):
+        shape = [1, 1, 1]
+        shape[ax] = n_a
+        ph += (torch.arange(n_a, dtype=torch.float64, device="cuda") * (k_a / n_a)).view(shape)
+    ph = torch.remainder(ph, 1.0) * (2 * np.pi)
+    wave = torch.complex(torch.cos(ph), torch.sin(ph)).to(torch.complex64).reshape(-1)
+    del ph
+    y = plan.forward(wave)
+    peak = y.view(dims)[k0].item()
+    y.view(dims)[k0] = 0
+    resid = float(torch.linalg.vector_norm(y.to(torch.complex128)))
+    print(f"nd 2^30 plane wave: peak {peak:.6e} (want {N}), residual {resid:.3e}", flush=True)
+    assert abs(peak - N) <= 2e-6 * 30 * N
+    assert resid <= 2e-6 * 30 * N
+    del y, wave
+    x = torch.rand(2 * N, dtype=torch.float32, device="cuda").mul_(2).sub_(1).view(torch.complex64)
+    z = plan.adjoint(plan.forward(x))
+    diff = float(torch.linalg.vector_norm((z - N * x).to(torch.complex128)))
+    ref = float(torch.linalg.vector_norm((N * x).to(torch.complex128)))
+    print(f"nd 2^30 round trip: rel err {diff / ref:.3e}", flush=True)
+    assert diff / ref <= 2 * 2e-6 * 30
+    plan.close()

@@ -164,3 +164,12 @@ def test_invalid_gated_bits():
     for bad in ([0, 0], [4], [-1]):
         with pytest.raises(ValueError):
             moa.gate_transpose_vector(4, bad)
+
+
+def test_source_of_subset_matches_full_table():
+    rng = np.random.default_rng(9)
+    for m in (3, 9, 14):
+        t = list(rng.permutation(m))
+        full = density.moa_source_offsets_fast(m, t)
+        idx = rng.integers(0, 1 << m, 50)
+        assert np.array_equal(density.hypercube_source_of(m, t, idx), full[idx])
