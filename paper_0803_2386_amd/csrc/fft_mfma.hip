@@ -357,25 +357,24 @@ __device__ __forceinline__ void split_pack(float xr, float xi, uint32_t& hw, uin
     }
 }
 
-// The NST radix-16 stages of the P columns (stride cs) held in LDS, in place
-// by decimation in time: the columns enter in base-16 digit-reversed order
-// and leave in natural order.  Stage s combines the slots that differ in
-// digit s: butterfly j of a block of 16^(s+1) slots reads slots
-// base + j + r 16^s, multiplies input r by omega_{16^(s+1)}^(j r) and writes
-// its output k back to slot base + j + k 16^s.  Each butterfly reads and
+// One radix-16 stage s of the P columns (stride cs) held in LDS, in place by
+// decimation in time: butterfly j of a block of 16^(s+1) slots reads slots
+// base + j + r 16^s, multiplies input r by omega_{16^(s+1)}^(j r) (TW: every
+// stage but the first), contracts the 16 inputs on the matrix cores and
+// writes output k back to slot base + j + k 16^s.  Each butterfly reads and
 // writes only its own 16 slots, so a wave stores its outputs as soon as the
-// contraction is done, and one barrier ends the stage.  Padded slot
-// base + r 16^s is pad(base) + r * pstep (pstep = 1 at s = 0, else
-// 16^s * 17 / 16).
-// fp16: the columns hold the tile times `down` (the tile scale), applied as
-// stage 0 reads them; the caller multiplies the result by the inverse.
-template <int LGN, int PREC, bool FWD, typename V8>
-__device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, float down, int t,
-                                                 const V8 (&ahi)[2], const V8 (&alo)[2])
+// contraction is done.  Padded slot base + r 16^s is pad(base) + r * pstep
+// (pstep = 1 at s = 0, else 16^s * 17 / 16).  A lane's four inputs are read,
+// and their twiddles formed, before any is used (one wait for the LDS, not
+// one per input); its twiddles are omega^(j 4g) * omega^(j i), i < 4, from two
+// table lookups.  SCALE (fp16, first stage): the inputs are multiplied by the
+// tile scale `mul` before the split.
+template <int LGN, int PREC, bool FWD, bool TW, bool SCALE, typename V8>
+__device__ __forceinline__ void mfma_stage(float2* lds, int cs, const float2* tl, float mul, int s, int t,
+                                           const V8 (&ahi)[2], const V8 (&alo)[2])
 {
     using Sp = SplitT<PREC>;
     constexpr int N = 1 << LGN;
-    constexpr int NST = LGN / 4;
     constexpr int NB = N / 16;  // butterflies per column per stage
     constexpr int GPW = 4;      // 16-butterfly groups per wave: 1024 butterflies, 16 waves
     const int lane = t & 63, wave = t >> 6, g = lane >> 4;
@@ -383,45 +382,65 @@ __device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const floa
         V8 v;
         uint32_t w[4];
     };
-    // One stage body for all stages (not unrolled: that keeps the register
-    // budget); the stage enters as uniform shifts and strides.
-#pragma unroll 1
-    for (int s = 0; s < NST; ++s) {
-        const int lgns = 4 * s, ns = 1 << lgns;
-        const int pstep = s == 0 ? 1 : ns + (ns >> 4);
-        const int tsh = kLgTwBlk - lgns - 4;
-        const float mul = (PREC == 2 && s == 0) ? down : 1.0f;
+    const int lgns = 4 * s, ns = 1 << lgns;
+    const int pstep = s == 0 ? 1 : ns + (ns >> 4);
+    const int tsh = kLgTwBlk - lgns - 4;
 #pragma unroll 2
-        for (int grp = 0; grp < GPW; ++grp) {
-            const int bf = (wave * GPW + grp) * 16 + (lane & 15);
-            const int w = bf >> (LGN - 4), b = bf & (NB - 1);
-            const int jj = b & (ns - 1);
-            float2* pb = lds + w * cs + lds_pad(((b >> lgns) << (lgns + 4)) + jj);
-            Op bhi, blo;
+    for (int grp = 0; grp < GPW; ++grp) {
+        const int bf = (wave * GPW + grp) * 16 + (lane & 15);
+        const int w = bf >> (LGN - 4), b = bf & (NB - 1);
+        const int jj = b & (ns - 1);
+        float2* pb = lds + w * cs + lds_pad(((b >> lgns) << (lgns + 4)) + jj);
+        float2 x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = pb[(4 * g + i) * pstep];
+        if constexpr (TW) {
+            const float2 w4 = tw_blk(tl, (jj * 4 * g) << tsh), w1 = tw_blk(tl, jj << tsh);
+            float2 f = w4;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int r = 4 * g + i;
-                float2 x = pb[r * pstep];
-                if (s > 0) x = cmul_fwd_or_conj(x, tw_blk(tl, (jj * r) << tsh), FWD);
-                float xr = x.x, xi = x.y;
-                if constexpr (PREC == 2) {
-                    xr *= mul;
-                    xi *= mul;
-                }
-                split_pack<PREC>(xr, xi, bhi.w[i], blo.w[i]);
-            }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = Sp::mma(ahi[h], bhi.v, acc);
-                acc = Sp::mma(ahi[h], blo.v, acc);
-                acc = Sp::mma(alo[h], bhi.v, acc);
-                // rows 4g .. 4g+3 of half h: outputs q = 8h + 2g and 8h + 2g + 1
-                const int q = 8 * h + 2 * g;
-                pb[q * pstep] = mkc(acc[0], acc[1]);
-                pb[(q + 1) * pstep] = mkc(acc[2], acc[3]);
+                x[i] = cmul_fwd_or_conj(x[i], f, FWD);
+                if (i < 3) f = cmul(f, w1);
             }
         }
+        Op bhi, blo;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float xr = x[i].x, xi = x[i].y;
+            if constexpr (SCALE) {
+                xr *= mul;
+                xi *= mul;
+            }
+            split_pack<PREC>(xr, xi, bhi.w[i], blo.w[i]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = Sp::mma(ahi[h], bhi.v, acc);
+            acc = Sp::mma(ahi[h], blo.v, acc);
+            acc = Sp::mma(alo[h], bhi.v, acc);
+            // rows 4g .. 4g+3 of half h: outputs q = 8h + 2g and 8h + 2g + 1
+            const int q = 8 * h + 2 * g;
+            pb[q * pstep] = mkc(acc[0], acc[1]);
+            pb[(q + 1) * pstep] = mkc(acc[2], acc[3]);
+        }
+    }
+}
+
+// The NST radix-16 stages of the P columns held in LDS: the columns enter in
+// base-16 digit-reversed order and leave in natural order.  The first stage
+// (no twiddles; fp16: the tile scale `down`) is peeled off the loop over the
+// others, which is not unrolled (that keeps the register budget).
+template <int LGN, int PREC, bool FWD, typename V8>
+__device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, float down, int t,
+                                                 const V8 (&ahi)[2], const V8 (&alo)[2])
+{
+    constexpr int NST = LGN / 4;
+    mfma_stage<LGN, PREC, FWD, false, PREC == 2>(lds, cs, tl, down, 0, t, ahi, alo);
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 1; s < NST; ++s) {
+        mfma_stage<LGN, PREC, FWD, true, false>(lds, cs, tl, 1.0f, s, t, ahi, alo);
         __syncthreads();
     }
 }
