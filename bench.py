@@ -154,7 +154,7 @@ def kernel_name(p):
         return "k_pass_pair<%d, %s, %s>" % (lg, tin, tout)
     if p["kernel_mode"] == 4:
         return "k_small<%d>" % lg
-    return "k_pass<float, %d, %d, %s, %s>" % (lg, p["kernel_mode"], tin, tout)
+    return "k_pass<float, %d, %d, %s, %s, %d>" % (lg, p["kernel_mode"], tin, tout, p["lg_radix"])
 
 
 def sources_digest(paths):
