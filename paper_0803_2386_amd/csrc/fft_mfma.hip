@@ -357,90 +357,169 @@ __device__ __forceinline__ void split_pack(float xr, float xi, uint32_t& hw, uin
     }
 }
 
-// One radix-16 stage s of the P columns (stride cs) held in LDS, in place by
-// decimation in time: butterfly j of a block of 16^(s+1) slots reads slots
-// base + j + r 16^s, multiplies input r by omega_{16^(s+1)}^(j r) (TW: every
-// stage but the first), contracts the 16 inputs on the matrix cores and
-// writes output k back to slot base + j + k 16^s.  Each butterfly reads and
-// writes only its own 16 slots, so a wave stores its outputs as soon as the
-// contraction is done.  Padded slot base + r 16^s is pad(base) + r * pstep
-// (pstep = 1 at s = 0, else 16^s * 17 / 16).  A lane's four inputs are read,
-// and their twiddles formed, before any is used (one wait for the LDS, not
-// one per input); its twiddles are omega^(j 4g) * omega^(j i), i < 4, from two
-// table lookups.  SCALE (fp16, first stage): the inputs are multiplied by the
-// tile scale `mul` before the split.
-template <int LGN, int PREC, bool FWD, bool TW, bool SCALE, typename V8>
-__device__ __forceinline__ void mfma_stage(float2* lds, int cs, const float2* tl, float mul, int s, int t,
-                                           const V8 (&ahi)[2], const V8 (&alo)[2])
+// The data of a stage are the A operand of the contraction (row c: the
+// butterfly, 32 columns: its 16 complex inputs, re and im interleaved; lane
+// (g, c) holds inputs 4g .. 4g+3 of butterfly c), the DFT matrix is the B
+// operand in two halves (columns: the real parts of the 16 outputs, then
+// their imaginary parts).  So lane (g, q) receives output q of butterflies
+// 4g .. 4g+3, real part from half 0 and imaginary part from half 1 -- which
+// is the A-operand layout of the next radix-16 stage when that stage's
+// butterfly q combines output q of these 16 butterflies: stages 0 and 1 of a
+// level run back to back in registers, with no exchange between them.
+
+// hi + lo split of a lane's four inputs into the A operand.
+template <int PREC, bool SCALE, typename V8>
+__device__ __forceinline__ void split_inputs(const float2 (&x)[4], float mul, V8& dhi, V8& dlo)
 {
-    using Sp = SplitT<PREC>;
-    constexpr int N = 1 << LGN;
-    constexpr int NB = N / 16;  // butterflies per column per stage
-    constexpr int GPW = 4;      // 16-butterfly groups per wave: 1024 butterflies, 16 waves
-    const int lane = t & 63, wave = t >> 6, g = lane >> 4;
     union Op {
         V8 v;
         uint32_t w[4];
-    };
+    } hi, lo;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float xr = x[i].x, xi = x[i].y;
+        if constexpr (SCALE) {
+            xr *= mul;
+            xi *= mul;
+        }
+        split_pack<PREC>(xr, xi, hi.w[i], lo.w[i]);
+    }
+    dhi = hi.v;
+    dlo = lo.v;
+}
+
+// Three split products per half: acc[h][i] = half h (re / im) of output q of
+// the lane's butterfly group rows 4g + i.
+template <int PREC, typename V8>
+__device__ __forceinline__ void contract(const V8& dhi, const V8& dlo, const V8 (&fhi)[2], const V8 (&flo)[2],
+                                         floatx4 (&acc)[2])
+{
+    using Sp = SplitT<PREC>;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        floatx4 a = {0.f, 0.f, 0.f, 0.f};
+        a = Sp::mma(dhi, fhi[h], a);
+        a = Sp::mma(dhi, flo[h], a);
+        a = Sp::mma(dlo, fhi[h], a);
+        acc[h] = a;
+    }
+}
+
+// x[i] * omega^(j (4g + i) 2^tsh), i < 4, from two table lookups:
+// omega^(4 g j) * omega^(i j).
+template <bool FWD>
+__device__ __forceinline__ void twiddle4(float2 (&x)[4], const float2* tl, int j, int g, int tsh)
+{
+    const float2 w4 = tw_blk(tl, (j * 4 * g) << tsh), w1 = tw_blk(tl, j << tsh);
+    float2 f = w4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x[i] = cmul_fwd_or_conj(x[i], f, FWD);
+        if (i < 3) f = cmul(f, w1);
+    }
+}
+
+// Stages 0 and 1 of the P columns held in LDS (entered in base-16
+// digit-reversed order): each group of 16 consecutive stage-0 butterflies is
+// one block of stage 1.  Stage 0 reads the block's 256 slots (slot 16 b + r,
+// input r of butterfly b; fp16: times the tile scale `mul`), contracts,
+// stage 1 twiddles its inputs (omega_256^(j r)) and contracts again, and the
+// outputs go back to the same 256 slots (output k of stage-1 butterfly j at
+// j + 16 k), all within one wave.
+template <int LGN, int PREC, bool FWD, typename V8>
+__device__ __forceinline__ void mfma_stages01(float2* lds, int cs, const float2* tl, float mul, int t,
+                                              const V8 (&fhi)[2], const V8 (&flo)[2])
+{
+    constexpr int N = 1 << LGN;
+    constexpr int NB = N / 16;  // butterflies per column per stage
+    constexpr int GPW = 4;      // 16-butterfly groups per wave: 1024 butterflies, 16 waves
+    const int lane = t & 63, wave = t >> 6, g = lane >> 4, c = lane & 15;
+#pragma unroll 2
+    for (int grp = 0; grp < GPW; ++grp) {
+        const int gb = (wave * GPW + grp) * 16;  // first butterfly of the group (flat)
+        const int w = gb >> (LGN - 4), b0 = gb & (NB - 1);
+        float2* col = lds + w * cs;
+        // stage 0: row c = butterfly b0 + c, inputs 4g .. 4g+3
+        float2 x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = col[mfma_lds_pad(16 * (b0 + c) + 4 * g + i)];
+        V8 dhi, dlo;
+        split_inputs<PREC, PREC == 2>(x, mul, dhi, dlo);
+        floatx4 acc[2];
+        contract<PREC>(dhi, dlo, fhi, flo, acc);
+        // stage 1: row c = butterfly j = c of the block, inputs r = 4g + i
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = mkc(acc[0][i], acc[1][i]);
+        twiddle4<FWD>(x, tl, c, g, kLgTwBlk - 8);
+        split_inputs<PREC, false>(x, 1.0f, dhi, dlo);
+        contract<PREC>(dhi, dlo, fhi, flo, acc);
+        // output k = c of stage-1 butterflies j = 4g + i: slot 16 b0 + j + 16 k
+        float2* ob = col + mfma_lds_pad(16 * b0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ob[4 * g + i + c * 17] = mkc(acc[0][i], acc[1][i]);
+    }
+}
+
+// One radix-16 stage s >= 2 of the P columns held in LDS, in place by
+// decimation in time: butterfly j of a block of 16^(s+1) slots reads slots
+// base + j + r 16^s, multiplies input r by omega_{16^(s+1)}^(j r), contracts
+// and writes output k back to slot base + j + k 16^s.  Padded slot
+// base + r 16^s is pad(base) + r * pstep, pstep = 16^s (1 + 1/16 + 1/256)
+// (16^s is a multiple of 256 from s = 2 on).  A lane
+// reads its four inputs (those of butterfly c of its group) and writes
+// output q = c of butterflies 4g .. 4g+3 of the group.
+template <int LGN, int PREC, bool FWD, typename V8>
+__device__ __forceinline__ void mfma_stage(float2* lds, int cs, const float2* tl, int s, int t,
+                                           const V8 (&fhi)[2], const V8 (&flo)[2])
+{
+    constexpr int N = 1 << LGN;
+    constexpr int NB = N / 16;
+    constexpr int GPW = 4;
+    const int lane = t & 63, wave = t >> 6, g = lane >> 4, c = lane & 15;
     const int lgns = 4 * s, ns = 1 << lgns;
-    const int pstep = s == 0 ? 1 : ns + (ns >> 4);
+    const int pstep = ns + (ns >> 4) + (ns >> 8);
     const int tsh = kLgTwBlk - lgns - 4;
 #pragma unroll 2
     for (int grp = 0; grp < GPW; ++grp) {
-        const int bf = (wave * GPW + grp) * 16 + (lane & 15);
-        const int w = bf >> (LGN - 4), b = bf & (NB - 1);
-        const int jj = b & (ns - 1);
-        float2* pb = lds + w * cs + lds_pad(((b >> lgns) << (lgns + 4)) + jj);
+        const int gb = (wave * GPW + grp) * 16;
+        const int w = gb >> (LGN - 4);
+        float2* col = lds + w * cs;
+        auto base = [&](int bf) {
+            const int b = bf & (NB - 1);
+            return mfma_lds_pad(((b >> lgns) << (lgns + 4)) + (b & (ns - 1)));
+        };
+        const int bin = gb + c;
         float2 x[4];
+        const float2* pin = col + base(bin);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = pb[(4 * g + i) * pstep];
-        if constexpr (TW) {
-            const float2 w4 = tw_blk(tl, (jj * 4 * g) << tsh), w1 = tw_blk(tl, jj << tsh);
-            float2 f = w4;
+        for (int i = 0; i < 4; ++i) x[i] = pin[(4 * g + i) * pstep];
+        twiddle4<FWD>(x, tl, bin & (ns - 1), g, tsh);
+        V8 dhi, dlo;
+        split_inputs<PREC, false>(x, 1.0f, dhi, dlo);
+        floatx4 acc[2];
+        contract<PREC>(dhi, dlo, fhi, flo, acc);
+        // the other rows' butterflies of the group are written only by this
+        // wave, and read by it before: a wave's LDS accesses keep their order
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                x[i] = cmul_fwd_or_conj(x[i], f, FWD);
-                if (i < 3) f = cmul(f, w1);
-            }
-        }
-        Op bhi, blo;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float xr = x[i].x, xi = x[i].y;
-            if constexpr (SCALE) {
-                xr *= mul;
-                xi *= mul;
-            }
-            split_pack<PREC>(xr, xi, bhi.w[i], blo.w[i]);
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = Sp::mma(ahi[h], bhi.v, acc);
-            acc = Sp::mma(ahi[h], blo.v, acc);
-            acc = Sp::mma(alo[h], bhi.v, acc);
-            // rows 4g .. 4g+3 of half h: outputs q = 8h + 2g and 8h + 2g + 1
-            const int q = 8 * h + 2 * g;
-            pb[q * pstep] = mkc(acc[0], acc[1]);
-            pb[(q + 1) * pstep] = mkc(acc[2], acc[3]);
-        }
+        for (int i = 0; i < 4; ++i) col[base(gb + 4 * g + i) + c * pstep] = mkc(acc[0][i], acc[1][i]);
     }
 }
 
 // The NST radix-16 stages of the P columns held in LDS: the columns enter in
-// base-16 digit-reversed order and leave in natural order.  The first stage
-// (no twiddles; fp16: the tile scale `down`) is peeled off the loop over the
-// others, which is not unrolled (that keeps the register budget).
+// base-16 digit-reversed order and leave in natural order.  Stages 0 and 1
+// run together in registers; the others (the 4096-point level's third) read
+// and write LDS.  The loop over those is not unrolled (register budget).
 template <int LGN, int PREC, bool FWD, typename V8>
 __device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, float down, int t,
-                                                 const V8 (&ahi)[2], const V8 (&alo)[2])
+                                                 const V8 (&fhi)[2], const V8 (&flo)[2])
 {
     constexpr int NST = LGN / 4;
-    mfma_stage<LGN, PREC, FWD, false, PREC == 2>(lds, cs, tl, down, 0, t, ahi, alo);
+    static_assert(NST >= 2, "the matrix-core pair levels have at least two radix-16 stages");
+    mfma_stages01<LGN, PREC, FWD>(lds, cs, tl, down, t, fhi, flo);
     __syncthreads();
 #pragma unroll 1
-    for (int s = 1; s < NST; ++s) {
-        mfma_stage<LGN, PREC, FWD, true, false>(lds, cs, tl, 1.0f, s, t, ahi, alo);
+    for (int s = 2; s < NST; ++s) {
+        mfma_stage<LGN, PREC, FWD>(lds, cs, tl, s, t, fhi, flo);
         __syncthreads();
     }
 }
@@ -551,7 +630,7 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
         if (h) __syncthreads();  // the first half has been read back everywhere
         V* cin = lds + ui * cs;
 #pragma unroll
-        for (int m = 0; m < E; ++m) cin[lds_pad(rev16<LGN / 4>(ji + m * TPC))] = vh[m];
+        for (int m = 0; m < E; ++m) cin[mfma_lds_pad(rev16<LGN / 4>(ji + m * TPC))] = vh[m];
         __syncthreads();
         if (h == 0) {
             if constexpr (PREC == 2) {
@@ -560,19 +639,21 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
                 for (int w = 0; w < 16; ++w) m = fmaxf(m, wmax[w]);
                 tile_scale(m, down, up);
             }
-            // A operand fragments of this lane (two 16-row halves of the real
-            // 32 x 32 DFT matrix, hi and lo parts) from the omega_16 entries
-            // of the in-block table: tl[128 + 8 e] = omega_{2^14}^(1024 e).
-            const int lane = t & 63, g = lane >> 4;
+            // B operand fragments of this lane (the DFT matrix, hi and lo
+            // parts): half 0 maps input (re, im) of point r to the real part
+            // of output q (c, -s), half 1 to its imaginary part (s, c), with
+            // c + i s = omega_16^(q r) from the in-block table:
+            // tl[128 + 8 e] = omega_{2^14}^(1024 e).  Lane (g, q) holds rows
+            // 8g .. 8g+7 (points 4g .. 4g+3) of column q.
+            const int lane = t & 63, g = lane >> 4, q = lane & 15;
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const int row = 16 * hh + (lane & 15), col = 8 * g + i;
-                    const int e = ((row >> 1) * (col >> 1)) & 15;
-                    const V w = tl[128 + 8 * e];
+                    const int r = 4 * g + (i >> 1), comp = i & 1;
+                    const V w = tl[128 + 8 * ((q * r) & 15)];
                     const float c = w.x, sn = FWD ? w.y : -w.y;  // forward table: w.y = -sin
-                    const float v = (row & 1) == 0 ? ((col & 1) == 0 ? c : -sn) : ((col & 1) == 0 ? sn : c);
+                    const float v = hh == 0 ? (comp == 0 ? c : -sn) : (comp == 0 ? sn : c);
                     const S hi = S(v);
                     ahi[hh][i] = hi;
                     alo[hh][i] = S(v - float(hi));
@@ -583,7 +664,7 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
         const V* cout = lds + uo * cs;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            vh[m] = cout[lds_pad(jo + m * TPC)];
+            vh[m] = cout[mfma_lds_pad(jo + m * TPC)];
             if constexpr (PREC == 2) vh[m] = mkc(vh[m].x * up, vh[m].y * up);
         }
     }

@@ -238,7 +238,9 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         d.kmode = 3;
         d.in_tile_fast = in_tf;
         d.out_tile_fast = out_tf;
-        d.col_stride = moa::lds_col_stride(1 << lgn, std::max(1, 16 / P));
+        const int lanes = std::max(1, 16 / P);
+        d.col_stride = d.mfma ? moa::lds_col_stride_of(moa::mfma_lds_padded_len(1 << lgn), lanes)
+                              : moa::lds_col_stride(1 << lgn, lanes);
         d.data_elems = P * d.col_stride;
         d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * (d.tw ? d.tw_parts : 0) +
                        (d.mfma ? moa::kMfmaScaleElems : 0)) * eb0;

@@ -23,6 +23,12 @@ def pad(i):
     return i + (i >> 4)
 
 
+def mfma_pad(i):
+    """LDS padding of the split-precision paired-column levels: one more spare
+    slot every 256 elements."""
+    return i + (i >> 4) + (i >> 8)
+
+
 def row_off(r, layout, stride):
     """Offset of row r of a DFT axis: blockwise when the layout has a block."""
     lg = layout["block_lg"]
@@ -254,7 +260,7 @@ def check_pass(p, total, elem_bytes):
     assert flat.size == total and np.array_equal(flat, np.arange(total)), "outputs not a permutation"
     # LDS slots
     cs = p["lds_col_stride"]
-    top = ((W // 2 if pair else W) - 1) * cs + pad(N - 1)
+    top = ((W // 2 if pair else W) - 1) * cs + (mfma_pad(N - 1) if mfma and pair else pad(N - 1))
     assert (top + 1) * elem_bytes <= p["lds_bytes"] <= 160 * 1024
 
 
@@ -419,3 +425,65 @@ def test_mfma_pair_stage_indexing(lgn):
         slots = new
     got = np.array([slots[pad(k)] for k in range(N)])
     assert np.abs(got - np.fft.fft(x)).max() < 1e-9 * N
+
+
+def _rev16(p, nst):
+    r = 0
+    for _ in range(nst):
+        r = (r << 4) | (p & 15)
+        p >>= 4
+    return r
+
+
+def _cycle_pairs_distinct(slots):
+    """8-byte LDS accesses of one wave instruction: each run of 16 lanes (one
+    LDS cycle) on 16 distinct bank pairs (slot mod 16)."""
+    a = np.asarray(slots).reshape(4, 16) % 16
+    return all(len(set(r.tolist())) == 16 for r in a)
+
+
+@pytest.mark.parametrize("n,lift", [(1 << 20, [256, 4096]), (1 << 16, [16, 4096]), (1 << 16, [256, 256])])
+def test_mfma_pair_lds_banks(n, lift):
+    """Every LDS access of the split-precision paired-column levels (the tile
+    scatter in digit-reversed order, the register-fused stages 0 and 1, the
+    in-place stages from 2 on, the natural-order readback) puts the 16 lanes
+    of each LDS cycle on distinct bank pairs, with the planned column stride.
+    Lane (g, c) = (lane / 16, lane % 16) of the matrix-core operand layout."""
+    h = capi.moa_fft_plan(n, 2, lift, prec=capi.MOA_FFT_PREC_SPLIT_FP16, flags=HOST)
+    d = _check_plan(h, n, 2, capi.MOA_C64)
+    seen = 0
+    for p in d["passes"]:
+        if p["mfma"] == "none" or p["kernel_mode"] != 3:
+            continue
+        seen += 1
+        N = p["N"]
+        lgn = N.bit_length() - 1
+        NB, TPC, P, nst = N // 16, N // 16, (1 << 14) // N, lgn // 4
+        cs = p["lds_col_stride"]
+        assert cs >= mfma_pad(N - 1) + 1
+        for wave in range(16):
+            t = wave * 64 + np.arange(64)
+            for tin in (False, True):
+                u = (t & (P - 1)) if tin else (t >> (lgn - 4))
+                j = (t >> (14 - lgn)) if tin else (t & (TPC - 1))
+                for m in range(16):
+                    assert _cycle_pairs_distinct([u[k] * cs + mfma_pad(_rev16(int(j[k]) + m * TPC, nst))
+                                                  for k in range(64)])
+                    assert _cycle_pairs_distinct(u * cs + mfma_pad(j + m * TPC))
+            g, c = np.arange(64) // 16, np.arange(64) % 16
+            for grp in range(4):
+                gb = (wave * 4 + grp) * 16
+                col = (gb >> (lgn - 4)) * cs
+                b0 = gb & (NB - 1)
+                for i in range(4):
+                    assert _cycle_pairs_distinct(col + mfma_pad(16 * (b0 + c) + 4 * g + i))
+                    assert _cycle_pairs_distinct(col + mfma_pad(16 * b0 + 4 * g + i + 16 * c))
+                    for s in range(2, nst):
+                        ns = 16 ** s
+
+                        def slot(bf, r):
+                            b = bf & (NB - 1)
+                            return col + mfma_pad(((b // ns) * ns * 16) + (b % ns) + r * ns)
+                        assert _cycle_pairs_distinct(slot(gb + c, 4 * g + i))
+                        assert _cycle_pairs_distinct(slot(gb + 4 * g + i, c))
+    assert seen >= 1
