@@ -33,6 +33,9 @@ constexpr int kTwBlkEntries = 256;
 // LDS elements after the tables of a matrix-core level: 16 floats, the
 // per-wave maxima from which an fp16 tile takes its scale.
 constexpr int kMfmaScaleElems = 8;
+// Then, in the paired-column matrix-core levels, the stage-1 twiddles of
+// every operand slot of a wave (64 lanes x 4).
+constexpr int kMfmaPairTwElems = 256;
 
 // LDS twiddle entries of the short-transform kernel: omega_N^e for e < N up
 // to 2^kLgSmallDirect points, else a copy of the in-block table.

@@ -351,9 +351,13 @@ __device__ __forceinline__ void split_pack(float xr, float xi, uint32_t& hw, uin
         lw = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){xr - hr, xi - hi}, h2v));
     } else {
         typedef _Float16 h2v __attribute__((ext_vector_type(2)));
-        const h2v h = __builtin_convertvector((f2v){xr, xi}, h2v);
-        hw = __builtin_bit_cast(uint32_t, h);
-        lw = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){xr - float(h.x), xi - float(h.y)}, h2v));
+        hw = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){xr, xi}, h2v));
+        // x - hi (exact) with the fp16 half read in place by one mixed-precision
+        // fused multiply-add a component: x + (-1) * hi
+        float lr, li;
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lr) : "v"(hw), "v"(xr));
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(li) : "v"(hw), "v"(xi));
+        lw = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){lr, li}, h2v));
     }
 }
 
@@ -423,11 +427,12 @@ __device__ __forceinline__ void twiddle4(float2 (&x)[4], const float2* tl, int j
 // digit-reversed order): each group of 16 consecutive stage-0 butterflies is
 // one block of stage 1.  Stage 0 reads the block's 256 slots (slot 16 b + r,
 // input r of butterfly b; fp16: times the tile scale `mul`), contracts,
-// stage 1 twiddles its inputs (omega_256^(j r)) and contracts again, and the
+// stage 1 twiddles its inputs (omega_256^(j r), j = c and r = 4g + i for
+// every group: the lane's four entries of the LDS table t1) and contracts again, and the
 // outputs go back to the same 256 slots (output k of stage-1 butterfly j at
 // j + 16 k), all within one wave.
 template <int LGN, int PREC, bool FWD, typename V8>
-__device__ __forceinline__ void mfma_stages01(float2* lds, int cs, const float2* tl, float mul, int t,
+__device__ __forceinline__ void mfma_stages01(float2* lds, int cs, const float2* t1, float mul, int t,
                                               const V8 (&fhi)[2], const V8 (&flo)[2])
 {
     constexpr int N = 1 << LGN;
@@ -448,9 +453,14 @@ __device__ __forceinline__ void mfma_stages01(float2* lds, int cs, const float2*
         floatx4 acc[2];
         contract<PREC>(dhi, dlo, fhi, flo, acc);
         // stage 1: row c = butterfly j = c of the block, inputs r = 4g + i
-#pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = mkc(acc[0][i], acc[1][i]);
-        twiddle4<FWD>(x, tl, c, g, kLgTwBlk - 8);
+        {
+            const float4* tw = reinterpret_cast<const float4*>(t1) + 2 * lane;
+            const float4 w01 = tw[0], w23 = tw[1];
+            x[0] = cmul_fwd_or_conj(mkc(acc[0][0], acc[1][0]), mkc(w01.x, w01.y), FWD);
+            x[1] = cmul_fwd_or_conj(mkc(acc[0][1], acc[1][1]), mkc(w01.z, w01.w), FWD);
+            x[2] = cmul_fwd_or_conj(mkc(acc[0][2], acc[1][2]), mkc(w23.x, w23.y), FWD);
+            x[3] = cmul_fwd_or_conj(mkc(acc[0][3], acc[1][3]), mkc(w23.z, w23.w), FWD);
+        }
         split_inputs<PREC, false>(x, 1.0f, dhi, dlo);
         contract<PREC>(dhi, dlo, fhi, flo, acc);
         // output k = c of stage-1 butterflies j = 4g + i: slot 16 b0 + j + 16 k
@@ -501,7 +511,12 @@ __device__ __forceinline__ void mfma_stage(float2* lds, int cs, const float2* tl
         // the other rows' butterflies of the group are written only by this
         // wave, and read by it before: a wave's LDS accesses keep their order
 #pragma unroll
-        for (int i = 0; i < 4; ++i) col[base(gb + 4 * g + i) + c * pstep] = mkc(acc[0][i], acc[1][i]);
+        for (int i = 0; i < 4; ++i) {
+            // real and imaginary parts stored separately: no register pairing
+            float* o = reinterpret_cast<float*>(col + base(gb + 4 * g + i) + c * pstep);
+            o[0] = acc[0][i];
+            o[1] = acc[1][i];
+        }
     }
 }
 
@@ -510,12 +525,12 @@ __device__ __forceinline__ void mfma_stage(float2* lds, int cs, const float2* tl
 // run together in registers; the others (the 4096-point level's third) read
 // and write LDS.  The loop over those is not unrolled (register budget).
 template <int LGN, int PREC, bool FWD, typename V8>
-__device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, float down, int t,
-                                                 const V8 (&fhi)[2], const V8 (&flo)[2])
+__device__ __forceinline__ void mfma_half_stages(float2* lds, int cs, const float2* tl, const float2* t1, float down,
+                                                 int t, const V8 (&fhi)[2], const V8 (&flo)[2])
 {
     constexpr int NST = LGN / 4;
     static_assert(NST >= 2, "the matrix-core pair levels have at least two radix-16 stages");
-    mfma_stages01<LGN, PREC, FWD>(lds, cs, tl, down, t, fhi, flo);
+    mfma_stages01<LGN, PREC, FWD>(lds, cs, t1, down, t, fhi, flo);
     __syncthreads();
 #pragma unroll 1
     for (int s = 2; s < NST; ++s) {
@@ -566,6 +581,17 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
             if (i < nt) tab[k] = i < 256 ? g1[i] : g2[i - 256];
         }
     }
+    // The stage-1 twiddle of operand slot (lane, i): omega_256^(c (4g + i)) =
+    // omega_{2^14}^e, e = 64 (c (4g + i) mod 256), the same for every group
+    // and both halves (a forward root; the adjoint conjugates it on use).
+    V t1v[2];
+    if (t < 256) {
+        const V* g1 = reinterpret_cast<const V*>(a.tw_blk);
+        const int l = t >> 2, i = t & 3;
+        const int e = 64 * (((l & 15) * (4 * (l >> 4) + i)) & 255);
+        t1v[0] = g1[e & 127];
+        t1v[1] = g1[128 + (e >> 7)];
+    }
     uint64_t tile = blockIdx.x;
     if (a.xcd_remap) tile = uint64_t(blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
     int64_t d0, ib, ob;
@@ -613,8 +639,10 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
         if (i < nt) tl[i] = tab[k];
     }
     // fp16: the largest |component| of the tile, one slot per wave after the
-    // tables (see the file comment).
+    // tables (see the file comment); then the stage-1 twiddles, lane-major.
     float* wmax = reinterpret_cast<float*>(tl + nt);
+    V* t1 = tl + nt + kMfmaScaleElems;
+    if (t < 256) t1[t] = cmul(t1v[0], t1v[1]);
     float down = 1.f, up = 1.f;
     if constexpr (PREC == 2) {
         float m = 0.f;
@@ -659,7 +687,7 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
                     alo[hh][i] = S(v - float(hi));
                 }
         }
-        mfma_half_stages<LGN, PREC, FWD>(lds, cs, tl, down, t, ahi, alo);
+        mfma_half_stages<LGN, PREC, FWD>(lds, cs, tl, t1, down, t, ahi, alo);
         // Read back in natural order (fp16: undoing the tile scale).
         const V* cout = lds + uo * cs;
 #pragma unroll

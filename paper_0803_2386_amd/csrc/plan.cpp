@@ -243,7 +243,7 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
                               : moa::lds_col_stride(1 << lgn, lanes);
         d.data_elems = P * d.col_stride;
         d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * (d.tw ? d.tw_parts : 0) +
-                       (d.mfma ? moa::kMfmaScaleElems : 0)) * eb0;
+                       (d.mfma ? moa::kMfmaScaleElems + moa::kMfmaPairTwElems : 0)) * eb0;
         if (d.lds_bytes > moa::kLdsBytes) return want_w > 0 ? MOA_ERR_TUNING : MOA_ERR_LIFT;
         d.threads = 1024;
         int64_t blocks = d.size[0] >> lgw_;
