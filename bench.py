@@ -374,38 +374,51 @@ def extras(args, torch, np, mfft, inputs):
         del xa, ya, za
 
     if want("split_mfma"):
-        # Split-precision matrix-core levels vs FP32, 256 x 2^20, lift <256 4096>.
-        n, B, lift = 1 << 20, 256, [256, 4096]
+        # Split-precision matrix-core levels vs FP32, 256 x 2^20, under both
+        # two-level lifts: <256 4096> (4096-point columns first, 64-byte runs)
+        # and <4096 256> (256-point columns first, 1 KB runs on both sides of
+        # each level).  Each figure is the median of three timed trials.
+        n, B = 1 << 20, 256
         xm = inputs.device_uniform_complex(n * B, args.seed + 3, torch.complex64, dev)
         ym = torch.empty_like(xm)
         rows = [0, B - 1]
         xs = xm.view(B, n)[rows].cpu().numpy()
-        rec = {"lift": lift}
-        for prec in ("native", "split_bf16", "split_fp16"):
-            p = mfft.Plan(n, B, lift, prec=prec)
-            d = p.describe()
-            p.forward(xm, out=ym)
-            mreps = max(3, reps // 2)
-            ms = time_events(lambda: p.forward(xm, out=ym), mreps, torch)
-            lv = level_times_in_chain(p, xm, ym, mreps, torch)
-            levels = len(d["passes"])
-            r = {"ms": round(ms, 4), "gflops": round(gflops(n, B, ms * 1e-3), 1),
-                 "hbm_gbs": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9, 1),
-                 "frac_hbm_peak": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                 "level_ms": [round(v, 4) for v in lv],
-                 "level_frac_hbm_peak": [round(16 * n * B / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for v in lv],
-                 "kernels": [kernel_name(q) for q in d["passes"]]}
-            stages = sum(int(math.log2(q["N"])) // 4 for q in d["passes"] if q["mfma"] != "none")
-            if stages:
-                # 6 MFMA 16x16x32 per 16 butterflies of a stage: 384 flops a point.
-                tf = 384.0 * stages * n * B / (ms * 1e-3) / 1e12
-                r["mfma_stages"] = stages
-                r["mfma_tflops"] = round(tf, 1)
-                r["mfma_frac_dense_peak"] = round(tf / MFMA_DENSE_PEAK_TFLOPS, 4)
-            bound = 2e-6 * math.log2(n) if prec != "split_bf16" else 2.0 * stages * 2.0 ** -16
-            samples["mfma_" + prec] = [(xs[i], ym.view(B, n)[rows[i]].cpu().numpy(), bound) for i in range(len(rows))]
-            rec[prec] = r
-            p.close()
+        rec = {}
+        best = {}
+        for lift in ([256, 4096], [4096, 256]):
+            lk = "lift_%dx%d" % tuple(lift)
+            rec[lk] = {}
+            for prec in ("native", "split_bf16", "split_fp16"):
+                p = mfft.Plan(n, B, lift, prec=prec)
+                d = p.describe()
+                p.forward(xm, out=ym)
+                mreps = max(3, reps // 2)
+                ms = sorted(time_events(lambda: p.forward(xm, out=ym), mreps, torch) for _ in range(3))[1]
+                lv = level_times_in_chain(p, xm, ym, mreps, torch)
+                levels = len(d["passes"])
+                r = {"ms": round(ms, 4), "gflops": round(gflops(n, B, ms * 1e-3), 1),
+                     "hbm_gbs": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm_peak": round(2 * levels * 8 * n * B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "level_ms": [round(v, 4) for v in lv],
+                     "level_frac_hbm_peak": [round(16 * n * B / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for v in lv],
+                     "kernels": [kernel_name(q) for q in d["passes"]]}
+                stages = sum(int(math.log2(q["N"])) // 4 for q in d["passes"] if q["mfma"] != "none")
+                if stages:
+                    # 6 MFMA 16x16x32 per 16 butterflies of a stage: 384 flops a point.
+                    tf = 384.0 * stages * n * B / (ms * 1e-3) / 1e12
+                    r["mfma_stages"] = stages
+                    r["mfma_tflops"] = round(tf, 1)
+                    r["mfma_frac_dense_peak"] = round(tf / MFMA_DENSE_PEAK_TFLOPS, 4)
+                bound = 2e-6 * math.log2(n) if prec != "split_bf16" else 2.0 * stages * 2.0 ** -16
+                samples["mfma_%s_%s" % (prec, lk)] = [(xs[i], ym.view(B, n)[rows[i]].cpu().numpy(), bound)
+                                                      for i in range(len(rows))]
+                rec[lk][prec] = r
+                if prec not in best or ms < best[prec][0]:
+                    best[prec] = (ms, lk)
+                p.close()
+        rec["best"] = {k: {"ms": round(v[0], 4), "lift": v[1]} for k, v in best.items()}
+        rec["split_over_native_at_best_lifts"] = {k: round(best[k][0] / best["native"][0], 4)
+                                                  for k in ("split_bf16", "split_fp16")}
         ex["split_mfma_b256_2^20"] = rec
         del xm, ym
 
@@ -689,10 +702,13 @@ def profile_run(args, torch, np, mfft, inputs):
             p.forward(x, out=y)
             p.adjoint(y, out=z)
     elif w.startswith("split_"):
+        # split_<prec>[_4096x256]: 256 x 2^20 under lift <256 4096>, or <4096 256>
         n, B = 1 << 20, 256
         x = inputs.device_uniform_complex(n * B, args.seed + 3, torch.complex64, dev)
         y = torch.empty_like(x)
-        p = mfft.Plan(n, B, [256, 4096], prec="native" if w == "split_native" else w)
+        prec = w[:-len("_4096x256")] if w.endswith("_4096x256") else w
+        lift = [4096, 256] if w.endswith("_4096x256") else [256, 4096]
+        p = mfft.Plan(n, B, lift, prec="native" if prec == "split_native" else prec)
         fn = lambda: p.forward(x, out=y)  # noqa: E731
     elif w in ("nd2", "nd3"):
         dims = (4096, 4096) if w == "nd2" else (256, 256, 256)
@@ -743,8 +759,9 @@ def main():
                          "(default all)")
     ap.add_argument("--profile", default=None,
                     help="kernel-only run for rocprofv3: warm-up, then --steps launches of one workload's kernels "
-                         "(headline, uneven, fwd_adj, split_native, split_bf16, split_fp16, nd2, nd3, hc_transpose, "
-                         "hc_gate), then a device copy of 128 MiB (the counters' reference); prints nothing else")
+                         "(headline, uneven, fwd_adj, split_native, split_bf16, split_fp16 -- each of the split "
+                         "ones also with the suffix _4096x256 for that lift --, nd2, nd3, hc_transpose, hc_gate), "
+                         "then a device copy of 128 MiB (the counters' reference); prints nothing else")
     ap.add_argument("--grid", type=int, default=1536,
                     help="--profile uneven: workgroups of the fused launch (the tuner's usual pick)")
     ap.add_argument("--copy-ref", action="store_true",

@@ -33,9 +33,6 @@ constexpr int kTwBlkEntries = 256;
 // LDS elements after the tables of a matrix-core level: 16 floats, the
 // per-wave maxima from which an fp16 tile takes its scale.
 constexpr int kMfmaScaleElems = 8;
-// Then, in the paired-column matrix-core levels, the stage-1 twiddles of
-// every operand slot of a wave (64 lanes x 4).
-constexpr int kMfmaPairTwElems = 256;
 
 // LDS twiddle entries of the short-transform kernel: omega_N^e for e < N up
 // to 2^kLgSmallDirect points, else a copy of the in-block table.
@@ -59,25 +56,15 @@ __host__ __device__ constexpr inline int lds_padded_len(int n) { return n + (n >
 // (the lanes served by one LDS cycle for 8-byte accesses) fall on distinct
 // 8-byte bank pairs: lanes_per_col consecutive rows of each of the
 // 16/lanes_per_col columns they cover.
-__host__ __device__ constexpr inline int lds_col_stride_of(int base, int lanes_per_col)
+__host__ __device__ constexpr inline int lds_col_stride(int n, int lanes_per_col)
 {
+    int base = lds_padded_len(n);
     int want = lanes_per_col >= 16 ? 0 : (lanes_per_col <= 0 ? 1 : lanes_per_col);
     if (want == 0) return base;
     int r = base & 31;
     int add = (want - r + 32) & 31;
     return base + add;
 }
-__host__ __device__ constexpr inline int lds_col_stride(int n, int lanes_per_col)
-{
-    return lds_col_stride_of(lds_padded_len(n), lanes_per_col);
-}
-
-// The split-precision paired-column levels add a spare slot after every 256
-// elements as well: their last radix-16 stage of a 4096-point column has the
-// 16 lanes of one LDS cycle write the 16 outputs of one butterfly, 256
-// elements apart -- one bank pair under the 16-element padding alone.
-__host__ __device__ constexpr inline int mfma_lds_pad(int i) { return i + (i >> 4) + (i >> 8); }
-__host__ __device__ constexpr inline int mfma_lds_padded_len(int n) { return mfma_lds_pad(n - 1) + 1; }
 
 // One pass of a lifted plan in operational normal form: a DFT of length
 // 2^lgn along one axis (in stride in_s_e, out stride out_s_k) for every

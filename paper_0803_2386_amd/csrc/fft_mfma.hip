@@ -29,6 +29,7 @@
 // on input and frequencies {2g, 2g+1, 8+2g, 9+2g} on output.  A wave works
 // on 8 groups of 16 butterflies per stage (32 points per thread).
 #include "fft_device.h"
+#include "fft_mfma_layout.h"
 
 namespace moa {
 

@@ -17,6 +17,7 @@
 
 #include "../../include/moa_fft.h"
 #include "fft_internal.h"
+#include "fft_mfma_layout.h"
 #include "psi.hpp"
 
 using moa::BatchTask;
@@ -239,8 +240,7 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         d.in_tile_fast = in_tf;
         d.out_tile_fast = out_tf;
         const int lanes = std::max(1, 16 / P);
-        d.col_stride = d.mfma ? moa::lds_col_stride_of(moa::mfma_lds_padded_len(1 << lgn), lanes)
-                              : moa::lds_col_stride(1 << lgn, lanes);
+        d.col_stride = d.mfma ? moa::mfma_lds_col_stride(1 << lgn, lanes) : moa::lds_col_stride(1 << lgn, lanes);
         d.data_elems = P * d.col_stride;
         d.lds_bytes = (d.data_elems + moa::kTwBlkEntries + 256 * (d.tw ? d.tw_parts : 0) +
                        (d.mfma ? moa::kMfmaScaleElems + moa::kMfmaPairTwElems : 0)) * eb0;
