@@ -18,7 +18,7 @@ def need_gpu():
         pytest.skip("no GPU")
 
 
-def test_config4_weighted_power_loss_gradient():
+def test_b256_n2p16_weighted_power_loss_gradient():
     """loss = sum_k w_k |FFT(x)_k|^2 over 256 x 2^16 (lift <256 256>); the
     gradient is the adjoint kernel applied to 2 w . X.  Eight seeded rows are
     checked against the FP64 analytic gradient 2 F^H (w . F x) of the oracle,
@@ -41,7 +41,7 @@ def test_config4_weighted_power_loss_gradient():
     err = float((np.linalg.norm(g - g_ref, axis=1) / np.linalg.norm(g_ref, axis=1)).max())
     yr = y.detach()[torch.from_numpy(rows).to(dev)].cpu().numpy().astype(np.complex128)
     L_rows = float((w_np * np.abs(yr) ** 2).sum())
-    print(f"config4 grad rel err {err:.3e}; loss(rows) {L_rows:.6e} vs {L_ref:.6e}", flush=True)
+    print(f"256 x 2^16 grad rel err {err:.3e}; loss(rows) {L_rows:.6e} vs {L_ref:.6e}", flush=True)
     # FP32 bound of one transform of n = 2^16 points: 2e-6 log2 n.
     tol = 2e-6 * 16
     assert err <= tol
@@ -71,7 +71,7 @@ def test_config4_weighted_power_loss_gradient():
             parts.append(loss_diff(xp, xm) / (2 * h))
         g_fd = parts[0] + 1j * parts[1]
         worst = max(worst, abs(g[0, j] - g_fd) / scale)
-    print(f"config4 GPU gradient vs FP64 central differences: max |diff| / rms(grad) = {worst:.3e}", flush=True)
+    print(f"256 x 2^16 GPU gradient vs FP64 central differences: max |diff| / rms(grad) = {worst:.3e}", flush=True)
     assert worst <= tol
 
 

@@ -52,7 +52,7 @@ def test_small_uneven_batch(per_size):
     check(sizes * 5, seed=1, threads=4, per_size=per_size)
 
 
-def test_config3_8192_transforms_2p6_to_2p14():
+def test_uneven_8192_transforms_2p6_to_2p14():
     need_gpu()
     sizes = inputs.uneven_sizes(8192, 6, 14, seed=0)
     import os

@@ -39,7 +39,7 @@ def rows_err(got, want):
 @pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
 @pytest.mark.parametrize("n,batch,lift", [(256, 64, None), (4096, 4, None), (1 << 16, 2, [16, 4096]),
                                           (1 << 16, 2, [256, 256]), (1 << 20, 2, [256, 4096]),
-                                          (1 << 12, 3, [16, 256])])
+                                          (1 << 12, 3, [16, 256]), (1 << 20, 2, [4096, 256])])
 def test_split_matches_oracle(prec, n, batch, lift):
     need_gpu()
     x = inputs.uniform_complex((batch, n), seed=n + batch, dtype=np.complex64)
@@ -57,9 +57,10 @@ def test_split_matches_oracle(prec, n, batch, lift):
         assert err <= bound(prec, n, stages)
 
 
-def test_config5_sampled_rows():
-    """256 transforms of 2^20 points through <256 4096>; the oracle checks
-    8 seeded rows of each precision."""
+@pytest.mark.parametrize("lift", [[256, 4096], [4096, 256]])
+def test_b256_n2p20_sampled_rows(lift):
+    """256 transforms of 2^20 points through either two-level lift; the
+    oracle checks 8 seeded rows of each precision."""
     need_gpu()
     n, B = 1 << 20, 256
     dev = torch.device("cuda", 0)
@@ -69,13 +70,13 @@ def test_config5_sampled_rows():
     want = oracle.fft_batch(xr, -1, threads=8)
     errs = {}
     for prec in ("native", "split_fp16", "split_bf16"):
-        plan = mfft.Plan(n, B, [256, 4096], prec=prec)
+        plan = mfft.Plan(n, B, lift, prec=prec)
         y = plan.forward(x).view(B, n)
         got = y[torch.from_numpy(rows).to(dev)].cpu().numpy().astype(np.complex128)
         errs[prec] = rows_err(got, want)
         plan.close()
         del y
-    print(f"config5 errors: {errs}", flush=True)
+    print(f"256 x 2^20 lift {lift} errors: {errs}", flush=True)
     assert errs["native"] <= 2e-6 * 20
     assert errs["split_fp16"] <= 2e-6 * 20
     assert errs["split_bf16"] <= 2.0 * 5 * 2.0 ** -16
