@@ -716,7 +716,7 @@ def profile_run(args, torch, np, mfft, inputs):
         y = torch.empty_like(x)
         p = mfft.NDPlan(dims, 1)
         fn = lambda: p.forward(x, out=y)  # noqa: E731
-    elif w in ("hc_transpose", "hc_gate"):
+    elif w in ("hc_transpose", "hc_gate", "hc_gate4"):
         from paper_0803_2386_amd import hypercube as hcube
         N = 1 << 13
         x = inputs.device_uniform_complex(N * N, args.seed + 4, torch.complex64, dev).view(N, N)
@@ -725,9 +725,12 @@ def profile_run(args, torch, np, mfft, inputs):
         if w == "hc_transpose":
             t = hcube.block_diagonal_transpose_vector(13, [0, 2])
             fn = lambda: hcube.hypercube_transpose(x.view(-1), t, out=y.view(-1))  # noqa: E731
-        else:
+        elif w == "hc_gate":
             U = torch.eye(4, dtype=torch.complex64, device=dev)
             fn = lambda: hcube.density_gate(y, U, [0, 2])  # noqa: E731
+        else:
+            U = torch.eye(16, dtype=torch.complex64, device=dev)
+            fn = lambda: hcube.density_gate(y, U, [0, 1, 2, 3])  # noqa: E731
     else:
         raise SystemExit(f"bench.py: unknown --profile workload {w!r}")
     for _ in range(args.warmup):
@@ -760,7 +763,7 @@ def main():
     ap.add_argument("--profile", default=None,
                     help="kernel-only run for rocprofv3: warm-up, then --steps launches of one workload's kernels "
                          "(headline, uneven, fwd_adj, split_native, split_bf16, split_fp16 -- each of the split "
-                         "ones also with the suffix _4096x256 for that lift --, nd2, nd3, hc_transpose, hc_gate), "
+                         "ones also with the suffix _4096x256 for that lift --, nd2, nd3, hc_transpose, hc_gate, hc_gate4), "
                          "then a device copy of 128 MiB (the counters' reference); prints nothing else")
     ap.add_argument("--grid", type=int, default=1536,
                     help="--profile uneven: workgroups of the fused launch (the tuner's usual pick)")

@@ -193,6 +193,107 @@ __global__ void __launch_bounds__(kThreads) k_density_gate(GateArgs a)
     for (int r = 0; r < PER; ++r) rho[base + lo + uint64_t(a.hi_addr[r])] = v[r];
 }
 
+// Four-qubit gate of a complex64 density matrix on the matrix cores.  One
+// wave takes a 16 x 16 block B of the tile at a time and forms C = B U^H,
+// then E = U C = U B U^H, with v_mfma_f32_16x16x4_f32 (FP32 operands and
+// accumulation, as the vector kernel), four real products per complex one:
+//   C = B U^H:  m = row i of B, n = row b of U, K = column l;
+//   E = U C:    m = row a of U, n = column b of C, K = row i of C.
+// Lane (g, x) = (lane / 16, lane % 16) holds, in K step s, the operand of K
+// index 4g + s.  In that K order the first product's accumulators (lane
+// (g, n): C[4g + j][n], j = 0..3) are the second's B operand as they stand,
+// and both products take the same U fragments U[x][4g + s]: a block leaves
+// LDS once and returns once.  (The vector kernel reads 16 entries of U from
+// LDS for every element of each product, which bounds it.)
+template <int PER>
+__global__ void __launch_bounds__(kThreads) k_density_gate4_mfma(GateArgs a)
+{
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    using C = float2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = reinterpret_cast<C*>(smem);
+    C* __restrict__ rho = reinterpret_cast<C*>(a.rho);
+    const uint32_t t = threadIdx.x;
+    const int nthr = 1 << a.lg_threads;
+    const uint64_t tile = blockIdx.x;
+    uint64_t base = 0;
+#pragma unroll
+    for (int j = 0; j < 2 * 15; ++j)
+        if (j < a.nt_bits) base |= ((tile >> j) & 1u) << a.nt_addr[j];
+    uint64_t lo = 0;
+#pragma unroll
+    for (int j = 0; j < kLgThreads; ++j)
+        if (j < a.lg_threads) lo |= uint64_t((t >> j) & 1u) << a.lo_addr[j];
+    C v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = rho[base + lo + uint64_t(a.hi_addr[r])];
+    // U fragments of this lane, behind the tile's loads.
+    const int lane = int(t & 63u), g = lane >> 4, x = lane & 15;
+    const C* __restrict__ u = reinterpret_cast<const C*>(a.gate);
+    float ur[4], ui[4], nui[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const C w = u[x * 16 + 4 * g + s];
+        ur[s] = w.x;
+        ui[s] = w.y;
+        nui[s] = -w.y;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) lds[pad(int(t) + (r << a.lg_threads))] = v[r];
+    // LDS offsets of U's row and column indices: x, and 4g + s.
+    auto dep = [&](int k, const int8_t* pos) {
+        int o = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((k >> b) & 1) o |= 1 << pos[b];
+        return o;
+    };
+    const int rx = dep(x, a.row_lds), cx = dep(x, a.col_lds);
+    int ca[4], rb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        ca[s] = dep(4 * g + s, a.col_lds);
+        rb[s] = dep(4 * g + s, a.row_lds);
+    }
+    __syncthreads();
+    const int nblk = 1 << a.blk_bits;
+    for (int beta = int(t >> 6); beta < nblk; beta += nthr >> 6) {
+        int bo = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxTileBits; ++j)
+            if (j < a.blk_bits) bo |= ((beta >> j) & 1) << a.blk_lds[j];
+        C bv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bv[s] = lds[pad(bo + rx + ca[s])];  // B[x][4g + s]
+        // C = B U^H: Re = Br Ur^T + Bi Ui^T, Im = Bi Ur^T - Br Ui^T.
+        floatx4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].x, ur[s], cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].y, ur[s], ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].y, ui[s], cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].x, nui[s], ci, 0, 0, 0);
+        }
+        // E = U C: Re = Ur Cr - Ui Ci, Im = Ur Ci + Ui Cr.
+        floatx4 er = {0.f, 0.f, 0.f, 0.f}, ei = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            er = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[s], cr[s], er, 0, 0, 0);
+            ei = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[s], ci[s], ei, 0, 0, 0);
+            er = __builtin_amdgcn_mfma_f32_16x16x4f32(nui[s], ci[s], er, 0, 0, 0);
+            ei = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[s], cr[s], ei, 0, 0, 0);
+        }
+        // The whole block was read by this wave above: in place.
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lds[pad(bo + rb[j] + cx)] = make_float2(er[j], ei[j]);  // E[4g + j][x]
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = lds[pad(int(t) + (r << a.lg_threads))];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) rho[base + lo + uint64_t(a.hi_addr[r])] = v[r];
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
@@ -211,18 +312,38 @@ hipError_t launch_transpose(const TransArgs& a, int64_t tiles, int lds_bytes, hi
     return hipGetLastError();
 }
 
+template <int PER>
+void launch_gate4_mfma(const GateArgs& a, dim3 g, dim3 b, int lds_bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_density_gate4_mfma<PER>), g, b, lds_bytes, s, a);
+}
+
 template <typename C, int Q>
 hipError_t launch_gate_q(const GateArgs& a, dim3 g, dim3 b, int lds_bytes, hipStream_t s)
 {
-    switch (a.tile_bits - a.lg_threads) {
-        case 0: hipLaunchKernelGGL((k_density_gate<C, Q, 1>), g, b, lds_bytes, s, a); break;
-        case 1: hipLaunchKernelGGL((k_density_gate<C, Q, 2>), g, b, lds_bytes, s, a); break;
-        case 2: hipLaunchKernelGGL((k_density_gate<C, Q, 4>), g, b, lds_bytes, s, a); break;
-        case 3: hipLaunchKernelGGL((k_density_gate<C, Q, 8>), g, b, lds_bytes, s, a); break;
-        case 4: hipLaunchKernelGGL((k_density_gate<C, Q, 16>), g, b, lds_bytes, s, a); break;
-        default: return hipErrorInvalidValue;
+    // Four complex64 qubits: the matrix-core kernel (256 threads, blocks of
+    // 16 x 16, at least one a tile).
+    if constexpr (Q == 4 && sizeof(C) == 8) {
+        switch (a.tile_bits - a.lg_threads) {
+            case 0: launch_gate4_mfma<1>(a, g, b, lds_bytes, s); break;
+            case 1: launch_gate4_mfma<2>(a, g, b, lds_bytes, s); break;
+            case 2: launch_gate4_mfma<4>(a, g, b, lds_bytes, s); break;
+            case 3: launch_gate4_mfma<8>(a, g, b, lds_bytes, s); break;
+            case 4: launch_gate4_mfma<16>(a, g, b, lds_bytes, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    } else {
+        switch (a.tile_bits - a.lg_threads) {
+            case 0: hipLaunchKernelGGL((k_density_gate<C, Q, 1>), g, b, lds_bytes, s, a); break;
+            case 1: hipLaunchKernelGGL((k_density_gate<C, Q, 2>), g, b, lds_bytes, s, a); break;
+            case 2: hipLaunchKernelGGL((k_density_gate<C, Q, 4>), g, b, lds_bytes, s, a); break;
+            case 3: hipLaunchKernelGGL((k_density_gate<C, Q, 8>), g, b, lds_bytes, s, a); break;
+            case 4: hipLaunchKernelGGL((k_density_gate<C, Q, 16>), g, b, lds_bytes, s, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
 }
 
 template <typename C>

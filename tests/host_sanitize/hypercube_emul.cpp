@@ -153,6 +153,57 @@ static void gate_case(int n, const std::vector<int32_t>& gated, bool c128, std::
                 addr_of[size_t(e)] = off;
             }
         }
+        if (!c128 && q == 4) {
+            // The matrix-core kernel's schedule: per block, lane (g, x)
+            // reads B[x][4g + s]; the first product's accumulator register j
+            // of lane (g, n) is C[4g + j][n]; the second product's is
+            // E[4g + j][n], stored at row 4g + j, column n.  One
+            // v_mfma_f32_16x16x4_f32 adds sum_gg A(lane 16 gg + m) B(lane
+            // 16 gg + n) to D[m][n].
+            CHECK(L.threads % 64 == 0);
+            auto Uf = [&](int lane, int s) { return U[size_t((lane & 15) * 16 + 4 * (lane >> 4) + s)]; };
+            for (int beta = 0; beta < nblk; ++beta) {
+                int bo = 0;
+                for (int j = 0; j < a.blk_bits; ++j) bo |= ((beta >> j) & 1) << a.blk_lds[j];
+                cd bv[64][4];
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int s = 0; s < 4; ++s) {
+                        const int e = bo + roff[lane & 15] + coff[4 * (lane >> 4) + s];
+                        CHECK(e < tile_elems);
+                        bv[lane][s] = lds[size_t(pad_slot(e))];
+                    }
+                double cr[64][4] = {}, ci[64][4] = {}, er[64][4] = {}, ei[64][4] = {};
+                for (int s = 0; s < 4; ++s)
+                    for (int m = 0; m < 16; ++m)
+                        for (int n = 0; n < 16; ++n) {
+                            const int lane = 16 * (m >> 2) + n, j = m & 3;  // D[m][n]
+                            for (int gg = 0; gg < 4; ++gg) {
+                                const cd av = bv[16 * gg + m][s], w = Uf(16 * gg + n, s);
+                                cr[lane][j] += av.real() * w.real() + av.imag() * w.imag();
+                                ci[lane][j] += av.imag() * w.real() - av.real() * w.imag();
+                            }
+                        }
+                for (int s = 0; s < 4; ++s)
+                    for (int m = 0; m < 16; ++m)
+                        for (int n = 0; n < 16; ++n) {
+                            const int lane = 16 * (m >> 2) + n, j = m & 3;
+                            for (int gg = 0; gg < 4; ++gg) {
+                                const cd w = Uf(16 * gg + m, s);
+                                const double br = cr[16 * gg + n][s], bi = ci[16 * gg + n][s];
+                                er[lane][j] += w.real() * br - w.imag() * bi;
+                                ei[lane][j] += w.real() * bi + w.imag() * br;
+                            }
+                        }
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < 4; ++j) {
+                        const int e = bo + roff[4 * (lane >> 4) + j] + coff[lane & 15];
+                        CHECK(e < tile_elems);
+                        lds[size_t(pad_slot(e))] = cd(er[lane][j], ei[lane][j]);
+                    }
+            }
+            for (int e = 0; e < tile_elems; ++e) got[addr_of[size_t(e)]] = lds[size_t(pad_slot(e))];
+            continue;
+        }
         // phase 1: columns, phase 2: rows (the kernel's task loops)
         for (int task = 0; task < nblk * D; ++task) {
             const int beta = task & (nblk - 1), l = task >> a.blk_bits;

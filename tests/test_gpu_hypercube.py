@@ -140,6 +140,42 @@ def test_permutation_gates_are_exact():
     assert np.array_equal(r.cpu().numpy(), rho[swapbits(i), swapbits(j)])
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_four_qubit_permutation_gates_are_exact(dtype):
+    """A 16 x 16 permutation gate moves elements without arithmetic error (on
+    complex64 the four-qubit gate runs on the matrix cores: products by 0 and
+    1 and sums with zeros are exact there too)."""
+    need_gpu()
+    rng = np.random.default_rng(17)
+    npd = np.complex64 if dtype == torch.complex64 else np.complex128
+    for n, gated in ((6, [0, 2, 3, 5]), (9, [8, 1, 4, 6]), (11, [10, 9, 0, 1])):
+        rho = rand_density(n, rng).astype(npd)
+        P = np.eye(16, dtype=npd)[rng.permutation(16)]
+        r = torch.from_numpy(rho).cuda()
+        hc.density_gate(r, torch.from_numpy(P).cuda(), gated)
+        want = density.apply_gate_blocks(rho.astype(np.complex128), P.astype(np.complex128), gated).astype(npd)
+        assert np.array_equal(r.cpu().numpy(), want), (n, gated)
+
+
+@pytest.mark.parametrize("gated", [[0, 1, 2, 3], [11, 12, 0, 5]])
+def test_large_four_qubit_gate(gated):
+    """13 qubits (2^26 complex64 elements), four qubits gated (the matrix-core
+    kernel): every element against the oracle's block route on the host."""
+    need_gpu()
+    n = 13
+    rng = np.random.default_rng(9)
+    N = 1 << n
+    rho = torch.randn(N, N, dtype=torch.complex64, device="cuda")
+    U = rand_unitary(16, rng).astype(np.complex64)
+    before = rho.cpu().numpy().astype(np.complex128)
+    hc.density_gate(rho, torch.from_numpy(U).cuda(), gated)
+    got = rho.cpu().numpy().astype(np.complex128)
+    want = density.apply_gate_blocks(before, U.astype(np.complex128), gated)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"four-qubit gate n=13 gated={gated} rel err {err:.3e}", flush=True)
+    assert err <= gate_tol(4, torch.complex64)
+
+
 def test_large_gate_sampled_blocks():
     """13 qubits (2^26 complex64 elements, 512 MiB), two qubits gated: every
     element checked against the oracle's block route on the host."""
