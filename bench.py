@@ -280,7 +280,7 @@ def extras(args, torch, np, mfft, inputs):
         rec["tasks"] = d["tasks"]
 
         def entry(ms, p):
-            return {"ms": round(ms, 5), "grid": p.describe()["persistent_blocks"],
+            return {"ms": round(ms, 5), "grid": p.describe()["persistent_blocks"], "task_lg": p.describe()["task_lg"],
                     "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
                     "hbm_gbs": round(16 * total / (ms * 1e-3) / 1e9, 1),
                     "frac_hbm_peak": round(16 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

@@ -133,7 +133,15 @@ typedef struct {
                                    i.e. a level that stores in its load
                                    pattern, with at most 512 threads.
                                    Anything else MOA_ERR_TUNING            */
-    int32_t reserved[5];
+    int32_t batch_task_lg;      /* uneven batch: log2 of the most points one
+                                   task (one workgroup's share) packs from
+                                   transforms of 2^13 points or fewer: 11,
+                                   12 or 13 (0 = 13); shorter tasks mean
+                                   more of them for the dispatcher to
+                                   balance.  A longer transform is one
+                                   task (a 2^14-point complex64 transform
+                                   too).  Anything else MOA_ERR_TUNING     */
+    int32_t reserved[4];
 } moa_fft_tuning_t;
 
 /*

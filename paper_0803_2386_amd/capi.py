@@ -55,7 +55,8 @@ class moa_fft_tuning_t(ctypes.Structure):
                 ("persistent_blocks", ctypes.c_int32),
                 ("stream", ctypes.c_int32),
                 ("lg_radix", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("batch_task_lg", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class MoaError(RuntimeError):
@@ -134,6 +135,7 @@ def _tuning(tuning):
     for i, v in enumerate(tuning.get("lg_radix", [])[:8]):
         packed |= (int(v) & 0xF) << (4 * i)
     t.lg_radix = packed
+    t.batch_task_lg = int(tuning.get("batch_task_lg", 0))
     return ctypes.pointer(t)
 
 

@@ -89,6 +89,7 @@ struct moa_fft_plan_s {
     std::vector<int64_t> toff;
     std::vector<std::pair<int, int>> size_ranges;  // (first task, tasks) per distinct size
     int batch_threads = 0, batch_lds = 0, batch_grid = 0, batch_data_elems = 0;
+    int batch_task_lg = 13;  // log2 of the most points a task packs
     // tables: element offsets in d_tables (units of one complex element)
     std::vector<double> tab_host;  // interleaved re/im, float64
     int64_t tw_blk_off = 0;
@@ -692,8 +693,8 @@ std::string describe_json(const moa_fft_plan_s* p)
     s += "]";
     if (p->batched) {
         add(",\"count\":%lld,\"tasks\":%zu,\"threads\":%d,\"lds_bytes\":%d,\"persistent_blocks\":%d,"
-            "\"per_size\":%s,\"sizes_by_task_group\":[",
-            (long long)p->sizes.size(), p->tasks.size(), p->batch_threads, p->batch_lds, p->batch_grid,
+            "\"task_lg\":%d,\"per_size\":%s,\"sizes_by_task_group\":[",
+            (long long)p->sizes.size(), p->tasks.size(), p->batch_threads, p->batch_lds, p->batch_grid, p->batch_task_lg,
             (p->flags & MOA_FFT_FLAG_PER_SIZE) ? "true" : "false");
         for (size_t i = 0; i < p->size_ranges.size(); ++i) {
             const auto& r = p->size_ranges[i];
@@ -897,8 +898,12 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
     const size_t eb = elem_bytes(p->fp64);
     // Tasks of up to 2^13 points on 512 threads, 16 points a thread (one
     // transform a thread when it is shorter than that), or one complex64
-    // transform of 2^14 points as two halves of 2^13.
+    // transform of 2^14 points as two halves of 2^13.  A tuned task size of
+    // 2^11 or 2^12 points packs fewer of the shorter transforms a task.
     const int T = 512;
+    const int task_lg = tuning && tuning->batch_task_lg ? tuning->batch_task_lg : 13;
+    if (task_lg < 11 || task_lg > 13) return MOA_ERR_TUNING;
+    p->batch_task_lg = task_lg;
     const int64_t count = int64_t(p->sizes.size());
     std::vector<int64_t> off(size_t(count) + 1, 0);
     std::vector<std::vector<int64_t>> by_lg(size_t(maxlg) + 1);
@@ -922,7 +927,9 @@ moa_status_t plan_uneven(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         const int lgt = split ? 13 : lg;
         const int tpc = 1 << (lgt - lgE(lgt, 4));
         const int cs = moa::lds_col_stride(1 << lgt, tpc);
-        const int per = split ? 1 : T / tpc;  // 2^(13 - lg) transforms of 16 points or more, T shorter ones
+        // 2^(13 - lg) transforms of 16 points or more, T shorter ones; a
+        // smaller task size scales that down (at least one transform).
+        const int per = split ? 1 : std::max(1, (T / tpc) >> (13 - task_lg));
         const bool uses_lds = lg > 4;  // a single register stage needs no exchange
         const int first_task = int(p->tasks.size());
         for (size_t k = 0; k < idx.size(); k += size_t(per)) {

@@ -248,11 +248,14 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
 
 
 def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 256, 512, 768, 1024, 1536, 2048),
-                 reps: int = 10, verbose: bool = False, streams: Iterable[int] = (0, 1, -1)) -> dict:
-    """Time grids of an uneven batch's fused launch (0 = one workgroup per
-    task, the default; smaller grids make it persistent), then the streaming
-    modes of its loads and stores (0 = by size, 1 = always, -1 = never) at the
-    best grid; returns the best tuning."""
+                 reps: int = 10, verbose: bool = False, streams: Iterable[int] = (0, 1, -1),
+                 task_lgs: Iterable[int] = (13, 12, 11)) -> dict:
+    """Time the task packing (log2 of the most points a task packs: 13, the
+    default, or fewer for more and shorter tasks) and the grid of an uneven
+    batch's fused launch (0 = one workgroup per task, the default; smaller
+    grids make it persistent), then the streaming modes of its loads and
+    stores (0 = by size, 1 = always, -1 = never) at the best of those;
+    returns the best tuning."""
     import torch
 
     from . import fft as mfft
@@ -262,16 +265,27 @@ def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 25
     x = _timing_input(torch, total, dtype, dev)
     out = torch.empty_like(x)
     best = None
-    for g in grids:
-        tuning = {"persistent_blocks": int(g)} if g else None
-        plan = mfft.BatchedPlan(sizes, dtype=dtype, tuning=tuning)
-        ms = _time_plan(torch, plan, x, out, reps)
-        grid = plan.describe()["persistent_blocks"]
-        plan.close()
-        if verbose:
-            print(f"tune batched grid={grid}: {ms:.4f} ms", flush=True)
-        if best is None or ms < best["ms"]:
-            best = {"tuning": tuning, "grid": grid, "ms": ms}
+    seen = set()
+    for tl in task_lgs:
+        for g in grids:
+            tuning = {}
+            if g:
+                tuning["persistent_blocks"] = int(g)
+            if tl != 13:
+                tuning["batch_task_lg"] = int(tl)
+            plan = mfft.BatchedPlan(sizes, dtype=dtype, tuning=tuning or None)
+            d = plan.describe()
+            grid = d["persistent_blocks"]
+            if (tl, grid) in seen:  # a grid at least the task count is one workgroup a task
+                plan.close()
+                continue
+            seen.add((tl, grid))
+            ms = _time_plan(torch, plan, x, out, reps)
+            plan.close()
+            if verbose:
+                print(f"tune batched task_lg={tl} tasks={d['tasks']} grid={grid}: {ms:.4f} ms", flush=True)
+            if best is None or ms < best["ms"]:
+                best = {"tuning": tuning or None, "grid": grid, "task_lg": tl, "ms": ms}
     for sm in streams:
         if sm == 0:
             continue
@@ -281,9 +295,9 @@ def tune_batched(sizes: Sequence[int], dtype=None, grids: Iterable[int] = (0, 25
         ms = _time_plan(torch, plan, x, out, reps)
         plan.close()
         if verbose:
-            print(f"tune batched grid={best['grid']} stream={sm}: {ms:.4f} ms", flush=True)
+            print(f"tune batched task_lg={best['task_lg']} grid={best['grid']} stream={sm}: {ms:.4f} ms", flush=True)
         if ms < best["ms"]:
-            best = {"tuning": tuning, "grid": best["grid"], "ms": ms}
+            best = {"tuning": tuning, "grid": best["grid"], "task_lg": best["task_lg"], "ms": ms}
     return best
 
 

@@ -339,6 +339,39 @@ def test_batched_grid_defaults_to_one_workgroup_per_task():
                      tuning={"persistent_blocks": -1}) == capi.MOA_ERR_TUNING
 
 
+def test_batched_task_packing():
+    """The task size of an uneven batch: at most 2^13 points a task by
+    default; 2^12 or 2^11 pack fewer of the shorter transforms a task (each
+    size group then has at least the tasks its points need at that size;
+    a transform longer than the task size is one task); other sizes are
+    refused."""
+    sizes = [64, 128, 64, 16384, 8, 8192, 8192, 1, 64, 2048, 4] * 40
+
+    def desc(tuning):
+        h = capi.moa_fft_plan_batched(sizes, flags=HOST, tuning=tuning)
+        try:
+            return json.loads(capi.moa_fft_describe(h))
+        finally:
+            capi.moa_fft_destroy(h)
+
+    base = desc(None)
+    assert base["task_lg"] == 13 and desc({"batch_task_lg": 13})["tasks"] == base["tasks"]
+    prev = base["tasks"]
+    for tl in (12, 11):
+        d = desc({"batch_task_lg": tl})
+        assert d["task_lg"] == tl and d["tasks"] > prev
+        prev = d["tasks"]
+        for g in d["sizes_by_task_group"]:
+            n, count = g["n"], sizes.count(g["n"])
+            if n >= 1 << tl:
+                assert g["tasks"] == count
+            else:
+                assert g["tasks"] >= -(-count * n // (1 << tl))
+    for bad in (10, 14, -1):
+        assert status_of(capi.moa_fft_plan_batched, sizes, flags=HOST,
+                         tuning={"batch_task_lg": bad}) == capi.MOA_ERR_TUNING
+
+
 def test_stream_choice():
     """Streaming loads of the caller's input: automatic while the input is at
     most 256 MiB, forced on or off by the tuning field, other values refused."""

@@ -71,6 +71,19 @@ def test_uneven_8192_transforms_2p6_to_2p14():
     assert np.array_equal(per.cpu().numpy().astype(np.complex128), r1["forward"])
 
 
+@pytest.mark.parametrize("task_lg", [11, 12])
+def test_tuned_task_packing(task_lg):
+    """Smaller tasks (at most 2^11 or 2^12 points packed a workgroup) match
+    the oracle, and give the same bits as the default packing: a transform's
+    arithmetic does not depend on which task carries it."""
+    need_gpu()
+    sizes = [int(s) for s in inputs.uneven_sizes(600, 0, 14, seed=9)]
+    r = check(sizes, seed=9, threads=4, tuning=dict(batch_task_lg=task_lg, persistent_blocks=97))
+    x = torch.from_numpy(inputs.uniform_complex(sum(sizes), seed=9, dtype=np.complex64)).cuda()
+    default = mfft.BatchedPlan(sizes).forward(x).cpu().numpy().astype(np.complex128)
+    assert np.array_equal(default, r["forward"])
+
+
 def test_persistent_grid_smaller_than_tasks():
     need_gpu()
     sizes = [1 << (6 + (i % 9)) for i in range(300)]
