@@ -9,7 +9,10 @@
 // the real 32 x 32 form of the DFT matrix,
 //     [Re y_q]   [ c  -s ] [Re x_p]
 //     [Im y_q] = [ s   c ] [Im x_p],   c + i s = omega_16^(p q),
-// is the A operand in two 16-row halves.  Each operand is split into a high
+// is the A operand in two 16-row halves.  (The paired-column kernel further
+// down swaps the roles: the butterflies are the 16 rows of A and the DFT
+// matrix is B, so that one stage's accumulators are the next stage's
+// operand; see there.)  Each operand is split into a high
 // and a low half-precision part (x = hi + lo); three products hi*hi + hi*lo +
 // lo*hi are accumulated in float32 (the lo*lo term is below the accumulated
 // rounding).  Twiddles, the inter-level factor and all other arithmetic stay
@@ -25,9 +28,9 @@
 //   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + i], i < 8
 //   B (32 x 16): lane l holds B[8 (l / 16) + i][l % 16], i < 8
 //   D (16 x 16): lane l holds D[4 (l / 16) + i][l % 16], i < 4
-// so lane l of a group owns points 4g..4g+3 (g = l / 16) of butterfly l % 16
-// on input and frequencies {2g, 2g+1, 8+2g, 9+2g} on output.  A wave works
-// on 8 groups of 16 butterflies per stage (32 points per thread).
+// so in k_pass_mfma lane l of a group owns points 4g..4g+3 (g = l / 16) of
+// butterfly l % 16 on input and frequencies {2g, 2g+1, 8+2g, 9+2g} on output.
+// A wave works on 8 groups of 16 butterflies per stage (32 points per thread).
 #include "fft_device.h"
 #include "fft_mfma_layout.h"
 
