@@ -266,12 +266,28 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         if (lds_for(lgw, in_tf && lgw > 0).second > moa::kLdsBytes) return MOA_ERR_TUNING;
     } else {
         // Default tile: 2^12 points (2^11 for c128), so that several
-        // workgroups share a CU and overlap each other's memory phases; a
+        // workgroups share a CU and overlap each other's memory phases.  A
         // tile whose digit 0 is a unit-stride side takes at least 4 columns
-        // (32-byte segments, the narrowest the L2 merges well), up to the
-        // thread limit, LDS and the digit itself.
+        // (32-byte segments, the narrowest the L2 merges well); complex64
+        // levels take at least 128-byte runs (16 columns), and 512-byte runs
+        // (up to 2^14 points) where the rows they read lie 16 KB or more
+        // apart and the level keeps at least 2048 such tiles.  Measured: a
+        // 256-point level reading rows 32 KB apart, 16 columns 1.03 ms and
+        // 64 columns 0.83 ms; 1024-point levels reading rows 8 and 32 KB
+        // apart, 4 columns 120 / 118 us and 16 columns 70 / 83 us; whole
+        // 2^24-point transforms <1024 1024> 0.182 -> 0.133 ms, <512 512>
+        // 0.144 -> 0.109 ms, <2048 2048> 0.190 -> 0.165 ms (<512 4096> 0.123
+        // -> 0.130 ms the one loss seen).  Each up to the thread limit, LDS
+        // and the digit itself.
         const int base_lg = fp64 ? 11 : 12;
-        const int target_lg = (in_tf || out_tf) ? std::max(base_lg, lgn + 2) : base_lg;
+        int target_lg = (in_tf || out_tf) ? std::max(base_lg, lgn + 2) : base_lg;
+        if (!fp64 && (in_tf || out_tf)) target_lg = std::max(target_lg, lgn + 4);
+        if (!fp64 && in_tf) {
+            int64_t points = int64_t(1) << lgn;
+            for (int i = 0; i < d.nd; ++i) points *= d.size[i];
+            if (d.in_s_e * int64_t(eb) >= 16384 && (points >> 14) >= 2048)
+                target_lg = std::max(target_lg, std::min(14, lgn + 6));
+        }
         lgw = std::min(min_lgw, lg0);
         while (lgw < lg0 && lgn + lgw + 1 <= std::max(target_lg, lgn + min_lgw) && threads_ok(lgw + 1) &&
                lds_for(lgw + 1, in_tf).second <= moa::kLdsBytes)
