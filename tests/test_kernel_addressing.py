@@ -487,3 +487,29 @@ def test_mfma_pair_lds_banks(n, lift):
                         assert _cycle_pairs_distinct(slot(gb + c, 4 * g + i))
                         assert _cycle_pairs_distinct(slot(gb + 4 * g + i, c))
     assert seen >= 1
+
+
+@pytest.mark.parametrize("n,batch,lift,widths", [
+    # 256-point levels: 16 columns (128-byte runs); 64 columns where the rows
+    # read lie 32 KB apart and 2^28 points leave 16384 tiles of 2^14
+    (1 << 16, 256, [256, 256], [16, 16]),
+    (1 << 20, 256, [4096, 256], [64, 8]),
+    (1 << 20, 16, [4096, 256], [16, 8]),     # 2^24 points: 1024 tiles of 2^14, too few
+    (1 << 20, 256, [256, 4096], [8, 16]),    # rows written 32 KB apart: 16 columns
+    # 1024- and 2048-point levels: 128-byte runs up to 2^14 points a tile
+    (1 << 20, 16, [1024, 1024], [16, 16]),
+    (1 << 22, 4, [2048, 2048], [8, 8]),
+    (1 << 18, 64, [512, 512], [16, 16]),
+    (1 << 18, 64, [4096, 64], [64, 8]),      # 64-point levels: 2^12 points, 64 columns
+    (1 << 24, 1, [4096, 4096], [8, 8]),      # paired columns
+])
+def test_default_tile_widths(n, batch, lift, widths):
+    """The planner's default tile of a level with a unit-stride tile side:
+    at least 128-byte runs, 512-byte runs where the rows read lie 16 KB or
+    more apart and at least 2048 tiles of 2^14 points remain."""
+    h = capi.moa_fft_plan(n, batch, lift, flags=HOST)
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    assert [p["tile_width"] for p in d["passes"]] == widths
