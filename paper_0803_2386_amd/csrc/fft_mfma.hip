@@ -343,7 +343,7 @@ __device__ __forceinline__ int rev16(int p)
 }
 
 // hi + lo split of one complex value into two packed 32-bit words (re in the
-// low half, im in the high half), as the B operand wants them.
+// low half, im in the high half), as the operands of the contraction hold them.
 template <int PREC>
 __device__ __forceinline__ void split_pack(float xr, float xi, uint32_t& hw, uint32_t& lw)
 {
