@@ -193,23 +193,48 @@ __global__ void __launch_bounds__(kThreads) k_density_gate(GateArgs a)
     for (int r = 0; r < PER; ++r) rho[base + lo + uint64_t(a.hi_addr[r])] = v[r];
 }
 
-// Four-qubit gate of a complex64 density matrix on the matrix cores.  One
-// wave takes a 16 x 16 block B of the tile at a time and forms C = B U^H,
-// then E = U C = U B U^H, with v_mfma_f32_16x16x4_f32 (FP32 operands and
-// accumulation, as the vector kernel), four real products per complex one:
+// Four-qubit gate of a density matrix on the matrix cores.  One wave takes a
+// 16 x 16 block B of the tile at a time and forms C = B U^H, then
+// E = U C = U B U^H, with v_mfma_f32_16x16x4_f32 for complex64 and
+// v_mfma_f64_16x16x4_f64 for complex128 (operands and accumulation in the
+// element's precision, as the vector kernel), four real products per
+// complex one:
 //   C = B U^H:  m = row i of B, n = row b of U, K = column l;
 //   E = U C:    m = row a of U, n = column b of C, K = row i of C.
 // Lane (g, x) = (lane / 16, lane % 16) holds, in K step s, the operand of K
-// index 4g + s.  In that K order the first product's accumulators (lane
-// (g, n): C[4g + j][n], j = 0..3) are the second's B operand as they stand,
-// and both products take the same U fragments U[x][4g + s]: a block leaves
-// LDS once and returns once.  (The vector kernel reads 16 entries of U from
+// index k(g, s), where k(g, j) is also the row of the accumulator register j
+// of lane (g, n): 4g + j for the f32 instruction, g + 4j for the f64 one
+// (measured lane layouts).  In that K order the first product's
+// accumulators (lane (g, n): C[k(g, j)][n]) are the second's B operand as
+// they stand, and both products take the same U fragments U[x][k(g, s)]: a
+// block leaves LDS once and returns once.  (The vector kernel reads 16 entries of U from
 // LDS for every element of each product, which bounds it.)
-template <int PER>
+template <typename C> struct GateMfma;
+template <> struct GateMfma<float2> {
+    using R = float;
+    typedef float R4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ int k(int g, int s) { return 4 * g + s; }
+    static __device__ __forceinline__ R4 mma(float x, float y, R4 acc)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc, 0, 0, 0);
+    }
+};
+template <> struct GateMfma<double2> {
+    using R = double;
+    typedef double R4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ int k(int g, int s) { return g + 4 * s; }
+    static __device__ __forceinline__ R4 mma(double x, double y, R4 acc)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+    }
+};
+
+template <typename C, int PER>
 __global__ void __launch_bounds__(kThreads) k_density_gate4_mfma(GateArgs a)
 {
-    typedef float floatx4 __attribute__((ext_vector_type(4)));
-    using C = float2;
+    using M = GateMfma<C>;
+    using R = typename M::R;
+    using R4 = typename M::R4;
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
     C* __restrict__ rho = reinterpret_cast<C*>(a.rho);
@@ -230,17 +255,17 @@ __global__ void __launch_bounds__(kThreads) k_density_gate4_mfma(GateArgs a)
     // U fragments of this lane, behind the tile's loads.
     const int lane = int(t & 63u), g = lane >> 4, x = lane & 15;
     const C* __restrict__ u = reinterpret_cast<const C*>(a.gate);
-    float ur[4], ui[4], nui[4];
+    R ur[4], ui[4], nui[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const C w = u[x * 16 + 4 * g + s];
+        const C w = u[x * 16 + M::k(g, s)];
         ur[s] = w.x;
         ui[s] = w.y;
         nui[s] = -w.y;
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r) lds[pad(int(t) + (r << a.lg_threads))] = v[r];
-    // LDS offsets of U's row and column indices: x, and 4g + s.
+    // LDS offsets of U's row and column indices: x, and k(g, s).
     auto dep = [&](int k, const int8_t* pos) {
         int o = 0;
 #pragma unroll
@@ -252,8 +277,8 @@ __global__ void __launch_bounds__(kThreads) k_density_gate4_mfma(GateArgs a)
     int ca[4], rb[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        ca[s] = dep(4 * g + s, a.col_lds);
-        rb[s] = dep(4 * g + s, a.row_lds);
+        ca[s] = dep(M::k(g, s), a.col_lds);
+        rb[s] = dep(M::k(g, s), a.row_lds);
     }
     __syncthreads();
     const int nblk = 1 << a.blk_bits;
@@ -264,28 +289,33 @@ __global__ void __launch_bounds__(kThreads) k_density_gate4_mfma(GateArgs a)
             if (j < a.blk_bits) bo |= ((beta >> j) & 1) << a.blk_lds[j];
         C bv[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) bv[s] = lds[pad(bo + rx + ca[s])];  // B[x][4g + s]
+        for (int s = 0; s < 4; ++s) bv[s] = lds[pad(bo + rx + ca[s])];  // B[x][k(g, s)]
         // C = B U^H: Re = Br Ur^T + Bi Ui^T, Im = Bi Ur^T - Br Ui^T.
-        floatx4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+        R4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].x, ur[s], cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].y, ur[s], ci, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].y, ui[s], cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s].x, nui[s], ci, 0, 0, 0);
+            cr = M::mma(bv[s].x, ur[s], cr);
+            ci = M::mma(bv[s].y, ur[s], ci);
+            cr = M::mma(bv[s].y, ui[s], cr);
+            ci = M::mma(bv[s].x, nui[s], ci);
         }
         // E = U C: Re = Ur Cr - Ui Ci, Im = Ur Ci + Ui Cr.
-        floatx4 er = {0.f, 0.f, 0.f, 0.f}, ei = {0.f, 0.f, 0.f, 0.f};
+        R4 er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            er = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[s], cr[s], er, 0, 0, 0);
-            ei = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[s], ci[s], ei, 0, 0, 0);
-            er = __builtin_amdgcn_mfma_f32_16x16x4f32(nui[s], ci[s], er, 0, 0, 0);
-            ei = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[s], cr[s], ei, 0, 0, 0);
+            er = M::mma(ur[s], cr[s], er);
+            ei = M::mma(ur[s], ci[s], ei);
+            er = M::mma(nui[s], ci[s], er);
+            ei = M::mma(ui[s], cr[s], ei);
         }
         // The whole block was read by this wave above: in place.
 #pragma unroll
-        for (int j = 0; j < 4; ++j) lds[pad(bo + rb[j] + cx)] = make_float2(er[j], ei[j]);  // E[4g + j][x]
+        for (int j = 0; j < 4; ++j) {
+            C e;
+            e.x = er[j];
+            e.y = ei[j];
+            lds[pad(bo + rb[j] + cx)] = e;  // E[k(g, j)][x]
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -312,24 +342,24 @@ hipError_t launch_transpose(const TransArgs& a, int64_t tiles, int lds_bytes, hi
     return hipGetLastError();
 }
 
-template <int PER>
+template <typename C, int PER>
 void launch_gate4_mfma(const GateArgs& a, dim3 g, dim3 b, int lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_density_gate4_mfma<PER>), g, b, lds_bytes, s, a);
+    hipLaunchKernelGGL((k_density_gate4_mfma<C, PER>), g, b, lds_bytes, s, a);
 }
 
 template <typename C, int Q>
 hipError_t launch_gate_q(const GateArgs& a, dim3 g, dim3 b, int lds_bytes, hipStream_t s)
 {
-    // Four complex64 qubits: the matrix-core kernel (256 threads, blocks of
-    // 16 x 16, at least one a tile).
-    if constexpr (Q == 4 && sizeof(C) == 8) {
+    // Four qubits: the matrix-core kernel (256 threads, blocks of 16 x 16,
+    // at least one a tile).
+    if constexpr (Q == 4) {
         switch (a.tile_bits - a.lg_threads) {
-            case 0: launch_gate4_mfma<1>(a, g, b, lds_bytes, s); break;
-            case 1: launch_gate4_mfma<2>(a, g, b, lds_bytes, s); break;
-            case 2: launch_gate4_mfma<4>(a, g, b, lds_bytes, s); break;
-            case 3: launch_gate4_mfma<8>(a, g, b, lds_bytes, s); break;
-            case 4: launch_gate4_mfma<16>(a, g, b, lds_bytes, s); break;
+            case 0: launch_gate4_mfma<C, 1>(a, g, b, lds_bytes, s); break;
+            case 1: launch_gate4_mfma<C, 2>(a, g, b, lds_bytes, s); break;
+            case 2: launch_gate4_mfma<C, 4>(a, g, b, lds_bytes, s); break;
+            case 3: launch_gate4_mfma<C, 8>(a, g, b, lds_bytes, s); break;
+            case 4: launch_gate4_mfma<C, 16>(a, g, b, lds_bytes, s); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

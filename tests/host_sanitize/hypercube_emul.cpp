@@ -153,22 +153,31 @@ static void gate_case(int n, const std::vector<int32_t>& gated, bool c128, std::
                 addr_of[size_t(e)] = off;
             }
         }
-        if (!c128 && q == 4) {
+        if (q == 4) {
             // The matrix-core kernel's schedule: per block, lane (g, x)
-            // reads B[x][4g + s]; the first product's accumulator register j
-            // of lane (g, n) is C[4g + j][n]; the second product's is
-            // E[4g + j][n], stored at row 4g + j, column n.  One
-            // v_mfma_f32_16x16x4_f32 adds sum_gg A(lane 16 gg + m) B(lane
-            // 16 gg + n) to D[m][n].
+            // reads B[x][k(g, s)]; the first product's accumulator register
+            // j of lane (g, n) is C[k(g, j)][n]; the second product's is
+            // E[k(g, j)][n], stored at row k(g, j), column n; k(g, j) = 4g + j
+            // for the f32 instruction, g + 4j for the f64 one.  One MFMA
+            // adds sum_gg A(lane 16 gg + m) B(lane 16 gg + n) to D[m][n],
+            // D[k(g, j)][n] being register j of lane 16 g + n.
             CHECK(L.threads % 64 == 0);
-            auto Uf = [&](int lane, int s) { return U[size_t((lane & 15) * 16 + 4 * (lane >> 4) + s)]; };
+            auto kk = [&](int g, int s) { return c128 ? g + 4 * s : 4 * g + s; };
+            auto Uf = [&](int lane, int s) { return U[size_t((lane & 15) * 16 + kk(lane >> 4, s))]; };
+            // (lane, register) of D[m][n]
+            int dl[16], dj[16];
+            for (int g = 0; g < 4; ++g)
+                for (int j = 0; j < 4; ++j) {
+                    dl[kk(g, j)] = 16 * g;
+                    dj[kk(g, j)] = j;
+                }
             for (int beta = 0; beta < nblk; ++beta) {
                 int bo = 0;
                 for (int j = 0; j < a.blk_bits; ++j) bo |= ((beta >> j) & 1) << a.blk_lds[j];
                 cd bv[64][4];
                 for (int lane = 0; lane < 64; ++lane)
                     for (int s = 0; s < 4; ++s) {
-                        const int e = bo + roff[lane & 15] + coff[4 * (lane >> 4) + s];
+                        const int e = bo + roff[lane & 15] + coff[kk(lane >> 4, s)];
                         CHECK(e < tile_elems);
                         bv[lane][s] = lds[size_t(pad_slot(e))];
                     }
@@ -176,7 +185,7 @@ static void gate_case(int n, const std::vector<int32_t>& gated, bool c128, std::
                 for (int s = 0; s < 4; ++s)
                     for (int m = 0; m < 16; ++m)
                         for (int n = 0; n < 16; ++n) {
-                            const int lane = 16 * (m >> 2) + n, j = m & 3;  // D[m][n]
+                            const int lane = dl[m] + n, j = dj[m];  // D[m][n]
                             for (int gg = 0; gg < 4; ++gg) {
                                 const cd av = bv[16 * gg + m][s], w = Uf(16 * gg + n, s);
                                 cr[lane][j] += av.real() * w.real() + av.imag() * w.imag();
@@ -186,7 +195,7 @@ static void gate_case(int n, const std::vector<int32_t>& gated, bool c128, std::
                 for (int s = 0; s < 4; ++s)
                     for (int m = 0; m < 16; ++m)
                         for (int n = 0; n < 16; ++n) {
-                            const int lane = 16 * (m >> 2) + n, j = m & 3;
+                            const int lane = dl[m] + n, j = dj[m];
                             for (int gg = 0; gg < 4; ++gg) {
                                 const cd w = Uf(16 * gg + m, s);
                                 const double br = cr[16 * gg + n][s], bi = ci[16 * gg + n][s];
@@ -196,7 +205,7 @@ static void gate_case(int n, const std::vector<int32_t>& gated, bool c128, std::
                         }
                 for (int lane = 0; lane < 64; ++lane)
                     for (int j = 0; j < 4; ++j) {
-                        const int e = bo + roff[4 * (lane >> 4) + j] + coff[lane & 15];
+                        const int e = bo + roff[kk(lane >> 4, j)] + coff[lane & 15];
                         CHECK(e < tile_elems);
                         lds[size_t(pad_slot(e))] = cd(er[lane][j], ei[lane][j]);
                     }

@@ -157,23 +157,25 @@ def test_four_qubit_permutation_gates_are_exact(dtype):
         assert np.array_equal(r.cpu().numpy(), want), (n, gated)
 
 
-@pytest.mark.parametrize("gated", [[0, 1, 2, 3], [11, 12, 0, 5]])
-def test_large_four_qubit_gate(gated):
-    """13 qubits (2^26 complex64 elements), four qubits gated (the matrix-core
-    kernel): every element against the oracle's block route on the host."""
+@pytest.mark.parametrize("n,dtype,gated", [(13, torch.complex64, [0, 1, 2, 3]), (13, torch.complex64, [11, 12, 0, 5]),
+                                            (12, torch.complex128, [0, 1, 2, 3]), (12, torch.complex128, [11, 10, 0, 5])])
+def test_large_four_qubit_gate(n, dtype, gated):
+    """2^26 complex64 or 2^24 complex128 elements, four qubits gated (the
+    matrix-core kernel, f32 or f64 instruction): every element against the
+    oracle's block route on the host."""
     need_gpu()
-    n = 13
     rng = np.random.default_rng(9)
     N = 1 << n
-    rho = torch.randn(N, N, dtype=torch.complex64, device="cuda")
-    U = rand_unitary(16, rng).astype(np.complex64)
+    npd = np.complex64 if dtype == torch.complex64 else np.complex128
+    rho = torch.randn(N, N, dtype=dtype, device="cuda")
+    U = rand_unitary(16, rng).astype(npd)
     before = rho.cpu().numpy().astype(np.complex128)
     hc.density_gate(rho, torch.from_numpy(U).cuda(), gated)
     got = rho.cpu().numpy().astype(np.complex128)
     want = density.apply_gate_blocks(before, U.astype(np.complex128), gated)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
-    print(f"four-qubit gate n=13 gated={gated} rel err {err:.3e}", flush=True)
-    assert err <= gate_tol(4, torch.complex64)
+    print(f"four-qubit gate n={n} {dtype} gated={gated} rel err {err:.3e}", flush=True)
+    assert err <= gate_tol(4, dtype)
 
 
 def test_large_gate_sampled_blocks():
