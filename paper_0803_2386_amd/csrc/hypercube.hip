@@ -99,14 +99,23 @@ __device__ __forceinline__ double2 cmadd_conj(double2 acc, double2 a, double2 b)
     return make_double2(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.y, b.x, fma(-a.x, b.y, acc.y)));
 }
 
+// The vector kernel (one to three qubits).  A task is NC columns (phase 1)
+// or rows (phase 2) of one block, so each entry of U read serves NC
+// elements: two for three complex64 qubits, whose U lives in LDS (complex128
+// keeps one: its register budget); one and two qubits read U (at most 16
+// values) at uniform addresses straight from global memory, which the
+// compiler keeps in scalar registers.
 template <typename C, int Q, int PER>
 __global__ void __launch_bounds__(kThreads) k_density_gate(GateArgs a)
 {
     constexpr int D = 1 << Q;
+    constexpr int NC = Q == 3 && sizeof(C) == 8 ? 2 : 1;  // columns (rows) a task
+    constexpr bool ULDS = Q >= 3;       // U from LDS (else from global memory, uniform)
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = reinterpret_cast<C*>(smem);
     const int tile_elems = 1 << a.tile_bits;
     C* ul = lds + pad(tile_elems);   // U, D x D
+    const C* __restrict__ ug = reinterpret_cast<const C*>(a.gate);
     C* __restrict__ rho = reinterpret_cast<C*>(a.rho);
     const uint32_t t = threadIdx.x;
     const int nthr = 1 << a.lg_threads;
@@ -122,7 +131,9 @@ __global__ void __launch_bounds__(kThreads) k_density_gate(GateArgs a)
     C v[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) v[r] = rho[base + lo + uint64_t(a.hi_addr[r])];
-    for (int i = int(t); i < D * D; i += nthr) ul[i] = reinterpret_cast<const C*>(a.gate)[i];
+    if constexpr (ULDS)
+        for (int i = int(t); i < D * D; i += nthr) ul[i] = ug[i];
+    auto U = [&](int i, int k) { return ULDS ? ul[i * D + k] : ug[i * D + k]; };
 #pragma unroll
     for (int r = 0; r < PER; ++r) lds[pad(int(t) + (r << a.lg_threads))] = v[r];
     // LDS offsets of U's row and column indices (uniform).
@@ -142,48 +153,66 @@ __global__ void __launch_bounds__(kThreads) k_density_gate(GateArgs a)
     }
     __syncthreads();
     const int nblk = 1 << a.blk_bits;
-    const int tasks = nblk * D;
-    // Phase 1: column l of block beta: B[., l] <- U B[., l].
+    const int tasks = nblk * (D / NC);
+    // Phase 1: columns l + c D / NC of block beta: B[., l] <- U B[., l].
     for (int task = int(t); task < tasks; task += nthr) {
         const int beta = task & (nblk - 1), l = task >> a.blk_bits;
         int bo = 0;
 #pragma unroll
         for (int j = 0; j < kMaxTileBits; ++j)
             if (j < a.blk_bits) bo |= ((beta >> j) & 1) << a.blk_lds[j];
-        const int c0 = bo + coff[l];
-        C x[D];
+        int c0[NC];
+        C x[NC][D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = lds[pad(c0 + roff[k])];
+        for (int c = 0; c < NC; ++c) {
+            c0[c] = bo + coff[l + c * (D / NC)];
+#pragma unroll
+            for (int k = 0; k < D; ++k) x[c][k] = lds[pad(c0[c] + roff[k])];
+        }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            C acc;
-            acc.x = 0;
-            acc.y = 0;
+            C acc[NC];
 #pragma unroll
-            for (int k = 0; k < D; ++k) acc = cmadd(acc, ul[i * D + k], x[k]);
-            lds[pad(c0 + roff[i])] = acc;
+            for (int c = 0; c < NC; ++c) acc[c].x = acc[c].y = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const C w = U(i, k);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] = cmadd(acc[c], w, x[c][k]);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) lds[pad(c0[c] + roff[i])] = acc[c];
         }
     }
     __syncthreads();
-    // Phase 2: row i of block beta: T[i, .] <- T[i, .] U^H.
+    // Phase 2: rows i + c D / NC of block beta: T[i, .] <- T[i, .] U^H.
     for (int task = int(t); task < tasks; task += nthr) {
         const int beta = task & (nblk - 1), i = task >> a.blk_bits;
         int bo = 0;
 #pragma unroll
         for (int j = 0; j < kMaxTileBits; ++j)
             if (j < a.blk_bits) bo |= ((beta >> j) & 1) << a.blk_lds[j];
-        const int r0 = bo + roff[i];
-        C x[D];
+        int r0[NC];
+        C x[NC][D];
 #pragma unroll
-        for (int l = 0; l < D; ++l) x[l] = lds[pad(r0 + coff[l])];
+        for (int c = 0; c < NC; ++c) {
+            r0[c] = bo + roff[i + c * (D / NC)];
+#pragma unroll
+            for (int l = 0; l < D; ++l) x[c][l] = lds[pad(r0[c] + coff[l])];
+        }
 #pragma unroll
         for (int b = 0; b < D; ++b) {
-            C acc;
-            acc.x = 0;
-            acc.y = 0;
+            C acc[NC];
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc = cmadd_conj(acc, x[l], ul[b * D + l]);
-            lds[pad(r0 + coff[b])] = acc;
+            for (int c = 0; c < NC; ++c) acc[c].x = acc[c].y = 0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                const C w = U(b, l);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] = cmadd_conj(acc[c], x[c][l], w);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) lds[pad(r0[c] + coff[b])] = acc[c];
         }
     }
     __syncthreads();

@@ -213,34 +213,40 @@ static void gate_case(int n, const std::vector<int32_t>& gated, bool c128, std::
             for (int e = 0; e < tile_elems; ++e) got[addr_of[size_t(e)]] = lds[size_t(pad_slot(e))];
             continue;
         }
-        // phase 1: columns, phase 2: rows (the kernel's task loops)
-        for (int task = 0; task < nblk * D; ++task) {
+        // phase 1: columns, phase 2: rows (the kernel's task loops: a task
+        // is NC columns or rows of a block, NC = 2 for three complex64 qubits)
+        const int NC = q == 3 && !c128 ? 2 : 1;
+        for (int task = 0; task < nblk * (D / NC); ++task) {
             const int beta = task & (nblk - 1), l = task >> a.blk_bits;
             int bo = 0;
             for (int j = 0; j < a.blk_bits; ++j) bo |= ((beta >> j) & 1) << a.blk_lds[j];
-            const int c0 = bo + coff[l];
-            cd x[16];
-            for (int k = 0; k < D; ++k) {
-                CHECK(c0 + roff[k] < tile_elems);
-                x[k] = lds[size_t(pad_slot(c0 + roff[k]))];
-            }
-            for (int i = 0; i < D; ++i) {
-                cd acc = 0;
-                for (int k = 0; k < D; ++k) acc += U[size_t(i * D + k)] * x[k];
-                lds[size_t(pad_slot(c0 + roff[i]))] = acc;
+            for (int c = 0; c < NC; ++c) {
+                const int c0 = bo + coff[l + c * (D / NC)];
+                cd x[16];
+                for (int k = 0; k < D; ++k) {
+                    CHECK(c0 + roff[k] < tile_elems);
+                    x[k] = lds[size_t(pad_slot(c0 + roff[k]))];
+                }
+                for (int i = 0; i < D; ++i) {
+                    cd acc = 0;
+                    for (int k = 0; k < D; ++k) acc += U[size_t(i * D + k)] * x[k];
+                    lds[size_t(pad_slot(c0 + roff[i]))] = acc;
+                }
             }
         }
-        for (int task = 0; task < nblk * D; ++task) {
+        for (int task = 0; task < nblk * (D / NC); ++task) {
             const int beta = task & (nblk - 1), i = task >> a.blk_bits;
             int bo = 0;
             for (int j = 0; j < a.blk_bits; ++j) bo |= ((beta >> j) & 1) << a.blk_lds[j];
-            const int r0_ = bo + roff[i];
-            cd x[16];
-            for (int l = 0; l < D; ++l) x[l] = lds[size_t(pad_slot(r0_ + coff[l]))];
-            for (int b = 0; b < D; ++b) {
-                cd acc = 0;
-                for (int l = 0; l < D; ++l) acc += x[l] * std::conj(U[size_t(b * D + l)]);
-                lds[size_t(pad_slot(r0_ + coff[b]))] = acc;
+            for (int c = 0; c < NC; ++c) {
+                const int r0_ = bo + roff[i + c * (D / NC)];
+                cd x[16];
+                for (int l = 0; l < D; ++l) x[l] = lds[size_t(pad_slot(r0_ + coff[l]))];
+                for (int b = 0; b < D; ++b) {
+                    cd acc = 0;
+                    for (int l = 0; l < D; ++l) acc += x[l] * std::conj(U[size_t(b * D + l)]);
+                    lds[size_t(pad_slot(r0_ + coff[b]))] = acc;
+                }
             }
         }
         for (int e = 0; e < tile_elems; ++e) got[addr_of[size_t(e)]] = lds[size_t(pad_slot(e))];
