@@ -504,10 +504,28 @@ def test_mfma_pair_lds_banks(n, lift):
     (1 << 24, 1, [4096, 4096], [8, 8]),      # paired columns
 ])
 def test_default_tile_widths(n, batch, lift, widths):
-    """The planner's default tile of a level with a unit-stride tile side:
-    at least 128-byte runs, 512-byte runs where the rows read lie 16 KB or
-    more apart and at least 2048 tiles of 2^14 points remain."""
+    """The planner's default tile of a complex64 level with a unit-stride
+    tile side: at least 128-byte runs, 512-byte runs where the rows read lie
+    16 KB or more apart and at least 2048 tiles of 2^14 points remain."""
     h = capi.moa_fft_plan(n, batch, lift, flags=HOST)
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    assert [p["tile_width"] for p in d["passes"]] == widths
+
+
+@pytest.mark.parametrize("n,batch,lift,widths", [
+    (1 << 20, 8, [1024, 1024], [8, 4]),      # read side: the largest tile, 2^13 points
+    (1 << 18, 32, [512, 512], [16, 4]),
+    (1 << 16, 128, [256, 256], [32, 8]),
+    (1 << 22, 2, [2048, 2048], [4, 4]),
+    (1 << 20, 8, [256, 4096], [2, 8]),       # write side only: 2^11 points
+])
+def test_default_tile_widths_c128(n, batch, lift, widths):
+    """Complex128 levels reading along a unit-stride tile side take the
+    largest tile (2^13 points); write-side tiles keep 2^11 points."""
+    h = capi.moa_fft_plan(n, batch, lift, capi.MOA_C128, flags=HOST)
     try:
         d = json.loads(capi.moa_fft_describe(h))
     finally:
