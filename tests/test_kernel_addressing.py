@@ -501,12 +501,16 @@ def test_mfma_pair_lds_banks(n, lift):
     (1 << 22, 4, [2048, 2048], [8, 8]),
     (1 << 18, 64, [512, 512], [16, 16]),
     (1 << 18, 64, [4096, 64], [64, 8]),      # 64-point levels: 2^12 points, 64 columns
+    (1 << 21, 8, [512, 4096], [8, 8]),       # writing rows 32 KB apart only: 2^12 points
+    (1 << 22, 4, [1024, 4096], [8, 4]),
     (1 << 24, 1, [4096, 4096], [8, 8]),      # paired columns
 ])
 def test_default_tile_widths(n, batch, lift, widths):
     """The planner's default tile of a complex64 level with a unit-stride
-    tile side: at least 128-byte runs, 512-byte runs where the rows read lie
-    16 KB or more apart and at least 2048 tiles of 2^14 points remain."""
+    tile side: at least 128-byte runs (a level that only writes along the
+    tile, rows 32 KB or more apart, keeps 2^12 points), 512-byte runs where
+    the rows read lie 16 KB or more apart and at least 2048 tiles of 2^14
+    points remain."""
     h = capi.moa_fft_plan(n, batch, lift, flags=HOST)
     try:
         d = json.loads(capi.moa_fft_describe(h))
