@@ -276,9 +276,8 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         // 64 columns 0.83 ms; 1024-point levels reading rows 8 and 32 KB
         // apart, 4 columns 120 / 118 us and 16 columns 70 / 83 us; whole
         // 2^24-point transforms <1024 1024> 0.182 -> 0.133 ms, <512 512>
-        // 0.144 -> 0.109 ms, <2048 2048> 0.190 -> 0.165 ms (<512 4096> 0.123
-        // -> 0.130 ms the one loss seen).  Each up to the thread limit, LDS
-        // and the digit itself.
+        // 0.144 -> 0.109 ms, <2048 2048> 0.190 -> 0.165 ms.  Each up to the
+        // thread limit, LDS and the digit itself.
         const int base_lg = fp64 ? 11 : 12;
         int target_lg = (in_tf || out_tf) ? std::max(base_lg, lgn + 2) : base_lg;
         // (A level that only writes along the tile, rows 32 KB or more apart,
