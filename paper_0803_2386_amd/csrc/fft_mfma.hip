@@ -660,9 +660,11 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
     for (int h = 0; h < 2; ++h) {
         V* vh = h ? v1 : v0;
         if (h) __syncthreads();  // the first half has been read back everywhere
-        V* cin = lds + ui * cs;
+        // Row ji + m TPC enters at padded slot pad(rev16(ji)) + m: m is the
+        // top base-16 digit, which reverses to the lowest, below any padding.
+        V* cin = lds + ui * cs + mfma_lds_pad(rev16<LGN / 4>(ji));
 #pragma unroll
-        for (int m = 0; m < E; ++m) cin[mfma_lds_pad(rev16<LGN / 4>(ji + m * TPC))] = vh[m];
+        for (int m = 0; m < E; ++m) cin[m] = vh[m];
         __syncthreads();
         if (h == 0) {
             if constexpr (PREC == 2) {
@@ -692,11 +694,13 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
                 }
         }
         mfma_half_stages<LGN, PREC, FWD>(lds, cs, tl, t1, down, t, ahi, alo);
-        // Read back in natural order (fp16: undoing the tile scale).
-        const V* cout = lds + uo * cs;
+        // Read back in natural order (fp16: undoing the tile scale): row
+        // jo + m TPC sits at padded slot pad(jo) + m TPC (1 + 1/16 + 1/256).
+        constexpr int RSTEP = TPC + TPC / 16 + TPC / 256;
+        const V* cout = lds + uo * cs + mfma_lds_pad(jo);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            vh[m] = cout[mfma_lds_pad(jo + m * TPC)];
+            vh[m] = cout[m * RSTEP];
             if constexpr (PREC == 2) vh[m] = mkc(vh[m].x * up, vh[m].y * up);
         }
     }
