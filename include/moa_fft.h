@@ -52,7 +52,10 @@ typedef enum { MOA_C64 = 0, MOA_C128 = 1 } moa_fft_dtype_t;
  * a dense 16-point DFT contraction on the matrix cores with each operand
  * split into a high and a low half-precision part (three products, float32
  * accumulation); the dense radix-n butterfly is the general-radix block of
- * Ch. 1 (Fig. radnbutterfly).  Other stages and all twiddles stay float32. */
+ * Ch. 1 (Fig. radnbutterfly).  Only levels of 16, 256 or 4096 points run
+ * on the matrix cores, and only where one tile gathers 2^11 points or more
+ * (a 16-point level of fewer than 128 transforms, a 256-point one of fewer
+ * than 8, runs in float32).  Other levels, and all twiddles, stay float32. */
 typedef enum {
     MOA_FFT_PREC_NATIVE = 0,
     MOA_FFT_PREC_SPLIT_BF16 = 1,
@@ -153,8 +156,12 @@ typedef struct {
  * on the next axis outwards.  The product must equal n, every factor must
  * be a power of two, and each factor must fit one workgroup (at most 2^14
  * points for MOA_C64, 2^13 for MOA_C128).  NULL/0 selects a default lift
- * with the fewest levels (one level when n itself fits).  The paper's
- * uniform blocking by c corresponds to <2^p_max c ... c>.
+ * with the fewest levels (one level when n itself fits).  With a SPLIT
+ * precision the default keeps that level count and, where it can, cuts the
+ * levels into 16-, 256- and 4096-point levels for the matrix cores (2^20:
+ * <4096 256>), leaving the bits that make no whole radix-16 digit to the
+ * first level.  The paper's uniform blocking by c corresponds to
+ * <2^p_max c ... c>.
  *
  * On success *out receives a new plan.  Errors: MOA_ERR_NULL (out NULL, or
  * lift_shape NULL with lift_rank > 0), MOA_ERR_SIZE, MOA_ERR_LIFT,
@@ -194,8 +201,8 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch,
  * SPLIT precision).  Errors: MOA_ERR_NULL (out or dims NULL), MOA_ERR_ARG
  * (rank outside 1..8, unknown or PER_SIZE flag), MOA_ERR_SIZE (an extent
  * that is not a power of two, too long, or a product above 2^30),
- * MOA_ERR_BATCH, MOA_ERR_DTYPE, MOA_ERR_LIFT (no kernel takes an axis, e.g.
- * a matrix-core axis with too few columns), MOA_ERR_ALLOC / MOA_ERR_HIP.
+ * MOA_ERR_BATCH, MOA_ERR_DTYPE, MOA_ERR_LIFT (no kernel takes an axis),
+ * MOA_ERR_ALLOC / MOA_ERR_HIP.
  * *out is untouched on error.  moa_fft_num_levels reports the launches;
  * moa_fft_exec_level(l) runs the l-th launch from `in` to `out`.
  */

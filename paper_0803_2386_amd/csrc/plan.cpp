@@ -338,6 +338,20 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
     return MOA_OK;
 }
 
+// finish_pass for a level that may run on the matrix cores: a matrix-core
+// tile holds at least 2^11 points, so a level with fewer transforms than that
+// (say 64 transforms of 16 points) runs its butterflies in FP32 instead,
+// unless the caller asked for a tile width.
+moa_status_t finish_pass_prec(PassDesc& d, bool fp64, int want_w, int cus)
+{
+    moa_status_t st = finish_pass(d, fp64, want_w, cus);
+    if (st == MOA_ERR_LIFT && d.mfma && want_w <= 0) {
+        d.mfma = 0;
+        st = finish_pass(d, fp64, want_w, cus);
+    }
+    return st;
+}
+
 void push_digit(PassDesc& d, int64_t size, int64_t in_s, int64_t out_s)
 {
     d.size[d.nd] = size;
@@ -432,7 +446,7 @@ moa_status_t lower(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         const int want = tuning ? tuning->cols_per_block[l] : 0;
         if (tuning && (want < 0)) return MOA_ERR_TUNING;
         d.lgrad = tuning ? int((tuning->lg_radix >> (4 * l)) & 0xFu) : 0;
-        moa_status_t st = finish_pass(d, p->fp64, want, p->cus);
+        moa_status_t st = finish_pass_prec(d, p->fp64, want, p->cus);
         if (st != MOA_OK) return st;
         // The level kernel applies the inter-level factor only when it stores
         // in its load pattern, which every non-final level of this lowering does.
@@ -486,7 +500,7 @@ moa_status_t lower_nd(moa_fft_plan_s* p, const moa_fft_tuning_t* tuning)
         const int want = tuning ? tuning->cols_per_block[l] : 0;
         if (want < 0) return MOA_ERR_TUNING;
         d.lgrad = tuning ? int((tuning->lg_radix >> (4 * l)) & 0xFu) : 0;
-        moa_status_t st = finish_pass(d, p->fp64, want, p->cus);
+        moa_status_t st = finish_pass_prec(d, p->fp64, want, p->cus);
         if (st != MOA_OK) return st;
         p->passes.push_back(d);
         p->levels.push_back(na);
@@ -1096,11 +1110,32 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
     } else {
         const int d = lg2(n);
         const int L = d <= maxlg ? 1 : (d + maxlg - 1) / maxlg;
-        // near-equal split, the outer levels take the remainder first
-        for (int i = 0; i < L; ++i) {
-            const int part = d / L + (i < d % L ? 1 : 0);
-            lift.push_back(int64_t(1) << part);
+        // Level sizes in pass order (innermost level first); lift is the reverse.
+        std::vector<int> parts;
+        if (prec != MOA_FFT_PREC_NATIVE) {
+            // Split precisions: the same number of levels (HBM passes) as
+            // in FP32, cut into whole radix-16 digits so that the levels run
+            // on the matrix cores (2^4, 2^8 and 2^12 points).  The bits that
+            // do not make a whole digit go to the first level, which runs in
+            // FP32 and takes as few bits as the 12-bit levels after it allow.
+            // The digits are spread evenly, the shorter levels first (2^20:
+            // <4096 256>, 1.85-2.05 ms against 2.07-2.25 ms for <256 4096>
+            // on 256 transforms).  Where no such cut exists (2^27, 2^28:
+            // two levels of at most 2^14 points) the FP32 lift is kept.
+            const int r = d % 4;
+            const int f = r == 0 && d <= 12 * L ? 0 : std::max(r, d - 12 * (L - 1));
+            const int k = f ? L - 1 : L;  // levels of whole digits
+            if (f <= maxlg && (k > 0 || f == d)) {
+                const int q = (d - f) / 4;
+                if (f) parts.push_back(f);
+                for (int i = 0; i < k; ++i) parts.push_back(4 * (q / k + (i >= k - q % k ? 1 : 0)));
+            }
         }
+        if (parts.empty()) {
+            // near-equal split, the outer levels take the remainder first
+            for (int i = L - 1; i >= 0; --i) parts.push_back(d / L + (i < d % L ? 1 : 0));
+        }
+        for (size_t i = parts.size(); i-- > 0;) lift.push_back(int64_t(1) << parts[i]);
     }
     moa_fft_plan_s* p = new (std::nothrow) moa_fft_plan_s();
     if (!p) return MOA_ERR_ALLOC;

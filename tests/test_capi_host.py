@@ -155,8 +155,8 @@ def test_batched_validation(sizes, want):
     assert status_of(capi.moa_fft_plan_batched, sizes, flags=HOST) == want
 
 
-def describe(n, batch=1, lift=None, dtype=capi.MOA_C64, tuning=None):
-    h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST, tuning=tuning)
+def describe(n, batch=1, lift=None, dtype=capi.MOA_C64, tuning=None, prec=capi.MOA_FFT_PREC_NATIVE):
+    h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, prec=prec, flags=HOST, tuning=tuning)
     try:
         return json.loads(capi.moa_fft_describe(h))
     finally:
@@ -173,6 +173,47 @@ def test_default_lifts():
     d = describe(1 << 24, lift=[4096, 4096])
     assert d["levels"] == [4096, 4096] and len(d["passes"]) == 2
     assert d["workspace_bytes"] == 8 << 24
+
+
+@pytest.mark.parametrize("prec", [capi.MOA_FFT_PREC_SPLIT_FP16, capi.MOA_FFT_PREC_SPLIT_BF16])
+def test_default_split_lifts_use_the_matrix_cores(prec):
+    """With a split precision the default lift keeps the FP32 level count but
+    cuts the levels into whole radix-16 digits, shorter levels first, so that
+    they run on the matrix cores; bits left over from whole digits go to the
+    first level, the only one that stays in FP32, and it takes as few as the
+    12-bit levels after it allow.  2^27 and 2^28 have no such cut into two
+    levels and keep the FP32 lift."""
+    want = {12: [4096], 16: [256, 256], 20: [4096, 256], 24: [4096, 4096], 13: [8192], 14: [16384],
+            15: [4096, 8], 17: [4096, 32], 19: [4096, 128], 22: [4096, 1024], 25: [4096, 8192],
+            26: [4096, 16384], 27: [16384, 8192], 28: [16384, 16384], 29: [4096, 4096, 32],
+            30: [4096, 4096, 64]}
+    for lg in range(1, 31):
+        d = describe(1 << lg, batch=64, prec=prec)
+        native = describe(1 << lg, batch=64)
+        assert len(d["passes"]) == len(native["passes"]), lg
+        assert lg in (4, 27, 28) or any(p["mfma"] != "none" for p in d["passes"]) or lg % 4 and lg < 15, lg
+    for lg, lift in want.items():
+        d = describe(1 << lg, batch=4, prec=prec)
+        assert d["lift"] == lift, lg
+        native = describe(1 << lg, batch=4)
+        assert len(d["passes"]) == len(native["passes"]), lg
+        # passes run innermost level first: the first takes the leftover bits
+        for i, p in enumerate(d["passes"]):
+            on_mfma = p["N"] in (16, 256, 4096)
+            assert (p["mfma"] != "none") == on_mfma, (lg, i)
+            assert on_mfma or i == 0 or lg in (27, 28), (lg, i)
+    # a length of at most 2^12 points stays one level; only 16, 256, 4096 use MFMA
+    assert describe(1 << 11, batch=64, prec=prec)["lift"] == [2048]
+    assert describe(1 << 8, batch=64, prec=prec)["passes"][0]["mfma"] != "none"
+    # a matrix-core tile gathers 2^11 points: with fewer transforms the level
+    # runs in FP32 (an explicit tile width below that stays an error)
+    assert describe(16, batch=128, prec=prec)["passes"][0]["mfma"] != "none"
+    assert describe(16, batch=64, prec=prec)["passes"][0]["mfma"] == "none"
+    assert describe(256, batch=4, lift=[256], prec=prec)["passes"][0]["mfma"] == "none"
+    assert describe(256, batch=8, lift=[256], prec=prec)["passes"][0]["mfma"] != "none"
+    with pytest.raises(capi.MoaError) as e:
+        describe(256, batch=64, lift=[256], prec=prec, tuning=dict(cols_per_block=[4]))
+    assert e.value.status == capi.MOA_ERR_TUNING
 
 
 def _row(k, layout, stride):

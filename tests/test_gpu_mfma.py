@@ -39,7 +39,8 @@ def rows_err(got, want):
 @pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
 @pytest.mark.parametrize("n,batch,lift", [(256, 64, None), (4096, 4, None), (1 << 16, 2, [16, 4096]),
                                           (1 << 16, 2, [256, 256]), (1 << 20, 2, [256, 4096]),
-                                          (1 << 12, 3, [16, 256]), (1 << 20, 2, [4096, 256])])
+                                          (1 << 12, 3, [16, 256]), (1 << 20, 2, [4096, 256]),
+                                          (1 << 20, 16, None), (1 << 19, 16, None)])
 def test_split_matches_oracle(prec, n, batch, lift):
     need_gpu()
     x = inputs.uniform_complex((batch, n), seed=n + batch, dtype=np.complex64)
@@ -55,6 +56,24 @@ def test_split_matches_oracle(prec, n, batch, lift):
         print(f"{prec} n={n} batch={batch} lift={lift} {name}: rel err {err:.3e} "
               f"(bound {bound(prec, n, stages):.2e}, {stages} MFMA stages)", flush=True)
         assert err <= bound(prec, n, stages)
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("n,batch,lift", [(16, 64, None), (256, 4, None), (256, 2, [16, 16])])
+def test_split_levels_with_too_few_transforms_run_fp32(prec, n, batch, lift):
+    """A matrix-core tile gathers 2^11 points; a level with fewer transforms
+    runs in FP32 under a split plan and meets the FP32 bound."""
+    need_gpu()
+    plan = mfft.Plan(n, batch, lift, prec=prec)
+    assert any(p["mfma"] == "none" and p["N"] in (16, 256) for p in plan.describe()["passes"])
+    x = inputs.uniform_complex((batch, n), seed=n + batch + 1, dtype=np.complex64)
+    t = torch.from_numpy(x).cuda()
+    for sign, fn in ((-1, plan.forward), (1, plan.adjoint)):
+        got = fn(t).cpu().numpy().astype(np.complex128).reshape(batch, n)
+        err = rows_err(got, oracle.fft(x.astype(np.complex128), sign))
+        stages = sum(int(np.log2(p["N"])) // 4 for p in plan.describe()["passes"] if p["mfma"] != "none")
+        print(f"{prec} n={n} batch={batch} lift={lift}: rel err {err:.3e}, {stages} MFMA stages", flush=True)
+        assert err <= max(2e-6 * np.log2(n), bound(prec, n, stages))
 
 
 @pytest.mark.parametrize("lift", [[256, 4096], [4096, 256]])
