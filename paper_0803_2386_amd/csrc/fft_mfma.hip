@@ -16,10 +16,10 @@
 // and a low half-precision part (x = hi + lo); three products hi*hi + hi*lo +
 // lo*hi are accumulated in float32 (the lo*lo term is below the accumulated
 // rounding).  Twiddles, the inter-level factor and all other arithmetic stay
-// float32.  For fp16 every tile is scaled on entry by an exact power of two
-// taken from its data, 2^-e with e the exponent of the largest |re| or |im|
-// of the tile, so that its values lie below 1 whatever the input's range,
-// and unscaled by 2^e on exit.  A radix-16 stage grows the largest value by
+// float32.  For fp16 every tile (in the paired-column kernel, every half
+// tile) is scaled on entry by an exact power of two taken from its data,
+// 2^-e with e the exponent of the largest |re| or |im| it holds, so that its
+// values lie below 1 whatever the input's range, and unscaled by 2^e on exit.  A radix-16 stage grows the largest value by
 // at most 16 (unit twiddles), so the input of stage s stays below 16^s
 // (256 at the third stage of a 4096-point level), inside fp16's range, and
 // values near the tile's largest keep their low part in the normal range.
@@ -551,8 +551,14 @@ __device__ __forceinline__ float2* mat(char* base, uint32_t off) { return reinte
 
 }  // namespace
 
-template <int LGN, int PREC, bool TIN, bool TOUT, bool FWD>
-__global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
+// One tile of a paired-column matrix-core level.  NTM picks the input load
+// policy: 0 = by a.nt_in at run time, 1 = streaming, 2 = cached.  With a
+// fixed policy the loads and their first uses share one straight-line path,
+// so each wait covers only the loads it needs: on a strided input the even
+// columns load first and the first half's LDS scatter and stages start while
+// the odd columns are still in flight.
+template <int LGN, int PREC, bool TIN, bool TOUT, bool FWD, int NTM>
+__device__ __forceinline__ void mfma_pair_tile(const PassArgs& a)
 {
     using V = float2;
     using Sp = SplitT<PREC>;
@@ -623,18 +629,30 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
             if (once) ld(true);
             else ld(false);
         } else {
+            // The even column first, then the odd one; the scheduling
+            // barriers keep that issue order.
             const uint32_t o0 = 2u * uint32_t(ui) * s0 + uint32_t(ji) * se, o1 = o0 + s0;
             auto ld = [&](bool nt) {
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const V* p0 = mat(gin, o0 + uint32_t(m) * step);
-                    const V* p1 = mat(gin, o1 + uint32_t(m) * step);
                     v0[m] = nt ? load_once(p0) : *p0;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const V* p1 = mat(gin, o1 + uint32_t(m) * step);
                     v1[m] = nt ? load_once(p1) : *p1;
                 }
+                __builtin_amdgcn_sched_barrier(0);
             };
-            if (once) ld(true);
-            else ld(false);
+            if constexpr (NTM == 0) {
+                if (once) ld(true);
+                else ld(false);
+            } else {
+                (void)once;
+                ld(NTM == 1);
+            }
         }
     }
 #pragma unroll
@@ -642,23 +660,26 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
         const int i = t + 1024 * k;
         if (i < nt) tl[i] = tab[k];
     }
-    // fp16: the largest |component| of the tile, one slot per wave after the
-    // tables (see the file comment); then the stage-1 twiddles, lane-major.
+    // fp16: the largest |component| of each half tile, one slot per wave
+    // after the tables (see the file comment); then the stage-1 twiddles,
+    // lane-major.
     float* wmax = reinterpret_cast<float*>(tl + nt);
     V* t1 = tl + nt + kMfmaScaleElems;
     if (t < 256) t1[t] = cmul(t1v[0], t1v[1]);
     float down = 1.f, up = 1.f;
-    if constexpr (PREC == 2) {
-        float m = 0.f;
-#pragma unroll
-        for (int k = 0; k < E; ++k) m = abs_max(v1[k], abs_max(v0[k], m));
-        m = wave_max(m);
-        if ((t & 63) == 0) wmax[t >> 6] = m;
-    }
     V8 ahi[2], alo[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         V* vh = h ? v1 : v0;
+        // (The second half's slots are written after the stage barriers of
+        // the first, which every wave passes only after reading them.)
+        if constexpr (PREC == 2) {
+            float m = 0.f;
+#pragma unroll
+            for (int k = 0; k < E; ++k) m = abs_max(vh[k], m);
+            m = wave_max(m);
+            if ((t & 63) == 0) wmax[t >> 6] = m;
+        }
         if (h) __syncthreads();  // the first half has been read back everywhere
         // Row ji + m TPC enters at padded slot pad(rev16(ji)) + m: m is the
         // top base-16 digit, which reverses to the lowest, below any padding.
@@ -666,13 +687,13 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
 #pragma unroll
         for (int m = 0; m < E; ++m) cin[m] = vh[m];
         __syncthreads();
-        if (h == 0) {
-            if constexpr (PREC == 2) {
-                float m = 0.f;
+        if constexpr (PREC == 2) {
+            float m = 0.f;
 #pragma unroll
-                for (int w = 0; w < 16; ++w) m = fmaxf(m, wmax[w]);
-                tile_scale(m, down, up);
-            }
+            for (int w = 0; w < 16; ++w) m = fmaxf(m, wmax[w]);
+            tile_scale(m, down, up);
+        }
+        if (h == 0) {
             // B operand fragments of this lane (the DFT matrix, hi and lo
             // parts): half 0 maps input (re, im) of point r to the real part
             // of output q (c, -s), half 1 to its imaginary part (s, c), with
@@ -737,6 +758,17 @@ __global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
             *mat(gout, o0 + uint32_t(m) * step) = v0[m];
             *mat(gout, o1 + uint32_t(m) * step) = v1[m];
         }
+    }
+}
+
+template <int LGN, int PREC, bool TIN, bool TOUT, bool FWD>
+__global__ void __launch_bounds__(1024) k_pass_mfma_pair(PassArgs a)
+{
+    if constexpr (TIN) {
+        mfma_pair_tile<LGN, PREC, TIN, TOUT, FWD, 0>(a);
+    } else {
+        if (a.nt_in) mfma_pair_tile<LGN, PREC, TIN, TOUT, FWD, 1>(a);
+        else mfma_pair_tile<LGN, PREC, TIN, TOUT, FWD, 2>(a);
     }
 }
 
