@@ -170,13 +170,30 @@ def _time_plan(torch, plan, x, out, reps: int) -> float:
     return s.elapsed_time(e) / reps
 
 
+def first_round_lifts(n: int, batch: int, dtype_code: int = capi.MOA_C64, prec: int = capi.MOA_FFT_PREC_NATIVE,
+                      max_levels: int = 3) -> List[List[int]]:
+    """The lifts the tuner times first, with the planner's defaults: every
+    lift of `lift_candidates` that plans.  With a split precision only those
+    with a level on the matrix cores, where any has one: a lift of FP32
+    levels only would answer a split-precision request with FP32."""
+    ok = []
+    for lift in lift_candidates(n, dtype_code, max_levels):
+        d = _plan_ok(n, batch, lift, dtype_code, prec, None)
+        if d is not None:
+            ok.append((lift, any(p["mfma"] != "none" for p in d["passes"])))
+    if prec != capi.MOA_FFT_PREC_NATIVE and any(m for _, m in ok):
+        return [lift for lift, m in ok if m]
+    return [lift for lift, _ in ok]
+
+
 def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: int = 3, reps: int = 10,
          candidates_limit: Optional[int] = None, use_cache: bool = True, verbose: bool = False,
          refine: int = 5, radix: bool = True) -> dict:
     """Time the candidate lifts/tile widths/radices for (n, batch) on the
     current device; returns {"lift", "tuning", "ms", "tried"} and caches it.
 
-    Rounds: every lift with the planner's defaults; every tile width for the
+    Rounds: every lift of `first_round_lifts` with the planner's defaults
+    (with a split precision, those with a matrix-core level); every tile width for the
     `refine` fastest lifts; then (radix=True) for the three fastest so far,
     each level's register radix changed one level at a time, and the best
     change of every level combined."""
@@ -209,8 +226,7 @@ def tune(n: int, batch: int = 1, dtype=None, prec: str = "native", max_levels: i
             if verbose:
                 print(f"tune n={n} batch={batch} lift={lift} tuning={tuning}: {ms:.4f} ms", flush=True)
 
-    run([(lift, None) for lift in lift_candidates(n, dcode, max_levels)
-         if _plan_ok(n, batch, lift, dcode, pcode, None) is not None])
+    run([(lift, None) for lift in first_round_lifts(n, batch, dcode, pcode, max_levels)])
     top = sorted(timed, key=lambda r: r["ms"])[:max(1, refine)]
     for r in top:
         run([c for c in candidates(n, batch, dcode, pcode, max_levels=len(r["lift"]))

@@ -122,3 +122,22 @@ def test_tuner_radix_round_picks_a_correct_plan(tmp_path, monkeypatch):
     err = float((np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)).max())
     print(f"tuned 64 x 2^14: {best['tuning']} {best['ms']:.4f} ms, err {err:.3e}", flush=True)
     assert err <= 2e-6 * 14
+
+
+def test_tuner_split_precision_keeps_the_matrix_cores(tmp_path, monkeypatch):
+    """Tuning a split-precision plan of 16 x 2^16 picks a lift with a
+    matrix-core level, and that plan meets the split-bf16 bound."""
+    need_gpu()
+    monkeypatch.setenv("MOA_FFT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    n, B = 1 << 16, 16
+    best = tune.tune(n, B, prec="split_bf16", reps=2, refine=2, radix=False, verbose=True)
+    plan = mfft.Plan(n, B, best["lift"], prec="split_bf16", tuning=best["tuning"])
+    stages = sum(int(np.log2(p["N"])) // 4 for p in plan.describe()["passes"] if p["mfma"] != "none")
+    assert stages >= 1
+    x = inputs.uniform_complex((B, n), 8, np.complex64)
+    got = plan.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.complex128)
+    want = oracle.fft(x.astype(np.complex128))
+    err = float((np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)).max())
+    print(f"tuned split bf16 16 x 2^16: {best['lift']} {best['tuning']} {best['ms']:.4f} ms, err {err:.3e}, "
+          f"{stages} MFMA stages", flush=True)
+    assert err <= 2.0 * stages * 2.0 ** -16

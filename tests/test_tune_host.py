@@ -48,3 +48,19 @@ def test_radix_candidates_change_one_level_and_plan():
     assert tune.radix_candidates(1 << 16, 4, [256, 256], None, capi.MOA_C128, 0) == []
     k = tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 3, None, 5, radix=False)
     assert k != tune._key("dev", capi.MOA_C64, 1 << 16, 8, 0, 3, None, 5, radix=True)
+
+
+def test_split_precision_tunes_matrix_core_lifts_only():
+    """A split-precision request is tuned over lifts with a level on the
+    matrix cores (16, 256 or 4096 points); FP32 tunes over every lift."""
+    n, B = 1 << 20, 256
+    native = tune.first_round_lifts(n, B)
+    assert [1024, 1024] in native and [4096, 256] in native
+    for prec in (capi.MOA_FFT_PREC_SPLIT_BF16, capi.MOA_FFT_PREC_SPLIT_FP16):
+        split = tune.first_round_lifts(n, B, prec=prec)
+        assert [4096, 256] in split and [256, 4096] in split and [16, 256, 256] in split
+        assert [1024, 1024] not in split and [512, 2048] not in split
+        assert all(any(f in (16, 256, 4096) for f in lift) for lift in split)
+        assert set(map(tuple, split)) < set(map(tuple, native))
+    # no lift of 2^2 points has a matrix-core level: split tunes over all of them
+    assert tune.first_round_lifts(4, 64, prec=capi.MOA_FFT_PREC_SPLIT_BF16) == tune.first_round_lifts(4, 64)
