@@ -282,10 +282,21 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         int target_lg = (in_tf || out_tf) ? std::max(base_lg, lgn + 2) : base_lg;
         // (A level that only writes along the tile, rows 32 KB or more apart,
         // keeps 2^12 points: 512- and 1024-point levels writing rows 32 KB
-        // apart were 9-10 % faster so than with 16 columns; a 2048-point
-        // level writing rows 16 KB apart was faster with 8 columns than 4.)
+        // apart ran 9-10 % faster that way than with 16 columns; a 2048-point
+        // level writing rows 16 KB apart was faster with 8 columns than 4.
+        // A 256-point one over 2^26 points or more, twice the Infinity Cache,
+        // takes 2^13 points, 32 columns: 256 x 2^20 <256 4096> 1.83 against
+        // 1.91 ms (1.90 with 64 columns), 64 x 2^20 0.499 against 0.515 ms,
+        // 16 x 2^24 <256 256 256> 2.79 against 2.85 ms; at 2^25 points and
+        // below 16 columns stay faster, 32 x 2^20 0.218-0.221 against
+        // 0.223-0.227 ms.)
         const bool far_writes = !in_tf && out_tf && d.out_s_k * int64_t(eb) >= 32768;
         if (!fp64 && (in_tf || out_tf) && !far_writes) target_lg = std::max(target_lg, lgn + 4);
+        if (!fp64 && far_writes && lgn == 8) {
+            int64_t points = int64_t(1) << lgn;
+            for (int i = 0; i < d.nd; ++i) points *= d.size[i];
+            if (points >= (int64_t(1) << 26)) target_lg = std::max(target_lg, 13);
+        }
         if (!fp64 && in_tf) {
             int64_t points = int64_t(1) << lgn;
             for (int i = 0; i < d.nd; ++i) points *= d.size[i];

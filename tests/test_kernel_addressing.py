@@ -495,7 +495,10 @@ def test_mfma_pair_lds_banks(n, lift):
     (1 << 16, 256, [256, 256], [16, 16]),
     (1 << 20, 256, [4096, 256], [64, 8]),
     (1 << 20, 16, [4096, 256], [16, 8]),     # 2^24 points: 1024 tiles of 2^14, too few
-    (1 << 20, 256, [256, 4096], [8, 16]),    # rows written 32 KB apart: 16 columns
+    (1 << 20, 256, [256, 4096], [8, 32]),    # rows written 32 KB apart, 2^28 points: 32 columns
+    (1 << 20, 32, [256, 4096], [8, 16]),     # 2^25 points (within twice the Infinity Cache): 16
+    (1 << 24, 1, [256, 256, 256], [16, 16, 16]),
+    (1 << 24, 4, [256, 256, 256], [64, 16, 32]),
     # 1024- and 2048-point levels: 128-byte runs up to 2^14 points a tile
     (1 << 20, 16, [1024, 1024], [16, 16]),
     (1 << 22, 4, [2048, 2048], [8, 8]),
@@ -508,7 +511,8 @@ def test_mfma_pair_lds_banks(n, lift):
 def test_default_tile_widths(n, batch, lift, widths):
     """The planner's default tile of a complex64 level with a unit-stride
     tile side: at least 128-byte runs (a level that only writes along the
-    tile, rows 32 KB or more apart, keeps 2^12 points), 512-byte runs where
+    tile, rows 32 KB or more apart, keeps 2^12 points, 2^13 at 256 points
+    over 2^26 points or more), 512-byte runs where
     the rows read lie 16 KB or more apart and at least 2048 tiles of 2^14
     points remain."""
     h = capi.moa_fft_plan(n, batch, lift, flags=HOST)
