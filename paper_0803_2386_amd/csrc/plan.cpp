@@ -284,18 +284,31 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         // keeps 2^12 points: 512- and 1024-point levels writing rows 32 KB
         // apart ran 9-10 % faster that way than with 16 columns; a 2048-point
         // level writing rows 16 KB apart was faster with 8 columns than 4.
-        // A 256-point one over 2^26 points or more, twice the Infinity Cache,
-        // takes 2^13 points, 32 columns: 256 x 2^20 <256 4096> 1.83 against
-        // 1.91 ms (1.90 with 64 columns), 64 x 2^20 0.499 against 0.515 ms,
-        // 16 x 2^24 <256 256 256> 2.79 against 2.85 ms; at 2^25 points and
-        // below 16 columns stay faster, 32 x 2^20 0.218-0.221 against
-        // 0.223-0.227 ms.)
+        // Once a buffer of the level outgrows the Infinity Cache, such levels
+        // of 256 .. 2048 points take 2^13 points and at least 128-byte runs
+        // up to 2^14 points: 32 columns at 256 points, 16 at 512 and 1024, 8
+        // at 2048; from 2^25 points (256 MiB), from 2^26 at 256 points.
+        // Measured, 2^28 points: <256 4096> 1.83 against 1.91 ms (16
+        // columns; 1.90 with 64), <512 4096> 1.94 against 2.18 ms (8; 2.24
+        // with 32), <1024 4096> 2.05-2.08 against 2.88-2.90 ms (4), <2048
+        // 4096> 2.20-2.22 against 3.16-3.20 ms (4), 2^30 <1024 1024 1024>
+        // 15.3 against 19.0 ms; 2^25 points: <512 4096> 0.252 against 0.318
+        // ms, <1024 4096> 0.275 against 0.452 ms, <2048 4096> 0.365 against
+        // 0.447 ms, but <256 4096> 0.224 against 0.215 ms with 16 columns;
+        // 2^24 points: the narrower tiles stay faster, <512 4096> 0.122
+        // against 0.128 ms, <1024 4096> 0.131 against 0.142 ms.  Complex128
+        // levels of 512 .. 2048 points take 128-byte runs (8 columns) up to
+        // 2^13 points from 256 MiB: 2^24 points <512 4096> 0.333 against
+        // 0.392 ms, <1024 4096> 0.353 against 0.383 ms, 2^25 points 0.667 /
+        // 0.694 against 0.759 / 0.781 ms; at 2^23 points they tie.)
         const bool far_writes = !in_tf && out_tf && d.out_s_k * int64_t(eb) >= 32768;
         if (!fp64 && (in_tf || out_tf) && !far_writes) target_lg = std::max(target_lg, lgn + 4);
-        if (!fp64 && far_writes && lgn == 8) {
-            int64_t points = int64_t(1) << lgn;
-            for (int i = 0; i < d.nd; ++i) points *= d.size[i];
-            if (points >= (int64_t(1) << 26)) target_lg = std::max(target_lg, 13);
+        if (far_writes && lgn >= 8 && lgn <= 11) {
+            int64_t bytes = (int64_t(1) << lgn) * eb;
+            for (int i = 0; i < d.nd; ++i) bytes *= d.size[i];
+            if (!fp64 && bytes >= (int64_t(1) << (lgn == 8 ? 29 : 28)))
+                target_lg = std::max(target_lg, std::min(14, std::max(13, lgn + 4)));
+            if (fp64 && lgn >= 9 && bytes >= (int64_t(1) << 28)) target_lg = std::max(target_lg, std::min(13, lgn + 3));
         }
         if (!fp64 && in_tf) {
             int64_t points = int64_t(1) << lgn;

@@ -115,6 +115,37 @@ def test_closed_forms_on_gpu():
         assert np.abs(got - want).max() < 2e-6 * np.log2(n) * np.sqrt(n) * 4
 
 
+@pytest.mark.parametrize("n,batch,lift,w1,dtype", [
+    (1 << 20, 256, [256, 4096], 32, torch.complex64), (1 << 21, 128, [512, 4096], 16, torch.complex64),
+    (1 << 22, 64, [1024, 4096], 16, torch.complex64), (1 << 23, 32, [2048, 4096], 8, torch.complex64),
+    (1 << 22, 8, [1024, 4096], 16, torch.complex64), (1 << 22, 4, [1024, 4096], 8, torch.complex128),
+    (1 << 21, 16, [512, 4096], 8, torch.complex128)])
+def test_far_writing_last_levels_beyond_the_infinity_cache(n, batch, lift, w1, dtype):
+    """256 MiB to 2 GiB whose last level writes rows 32 KB apart, on the
+    wide default tiles such levels take once a buffer outgrows the Infinity
+    Cache (complex64: 32 columns at 256 points, 16 at 512 and 1024, 8 at
+    2048; complex128: 8 columns): three seeded rows of each direction
+    against the oracle."""
+    need_gpu()
+    dev = torch.device("cuda", 0)
+    x = inputs.device_uniform_complex(n * batch, 28, dtype, dev)
+    plan = mfft.Plan(n, batch, lift, dtype=dtype)
+    assert plan.describe()["passes"][-1]["tile_width"] == w1
+    rows = np.random.default_rng(n).choice(batch, 3, replace=False)
+    ridx = torch.from_numpy(rows).to(dev)
+    xr = x.view(batch, n)[ridx].cpu().numpy().astype(np.complex128)
+    for name, sign, fn in (("forward", -1, plan.forward), ("adjoint", 1, plan.adjoint)):
+        y = fn(x)
+        got = y.view(batch, n)[ridx].cpu().numpy().astype(np.complex128)
+        del y
+        err = rel_err_rows(got, oracle.fft_batch(xr, sign, threads=8))
+        print(f"{batch} x {n} {lift} {dtype} {name}: rel err {err:.3e}", flush=True)
+        assert err <= tol(n, dtype)
+    plan.close()
+    del x
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 def test_maximum_size_sparse_spectrum(dtype):
     """n = 2^30, the largest size the library plans (default lift).  The input

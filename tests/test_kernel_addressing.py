@@ -496,7 +496,7 @@ def test_mfma_pair_lds_banks(n, lift):
     (1 << 20, 256, [4096, 256], [64, 8]),
     (1 << 20, 16, [4096, 256], [16, 8]),     # 2^24 points: 1024 tiles of 2^14, too few
     (1 << 20, 256, [256, 4096], [8, 32]),    # rows written 32 KB apart, 2^28 points: 32 columns
-    (1 << 20, 32, [256, 4096], [8, 16]),     # 2^25 points (within twice the Infinity Cache): 16
+    (1 << 20, 32, [256, 4096], [8, 16]),     # 256 points: 32 columns from 2^26 points only
     (1 << 24, 1, [256, 256, 256], [16, 16, 16]),
     (1 << 24, 4, [256, 256, 256], [64, 16, 32]),
     # 1024- and 2048-point levels: 128-byte runs up to 2^14 points a tile
@@ -506,13 +506,21 @@ def test_mfma_pair_lds_banks(n, lift):
     (1 << 18, 64, [4096, 64], [64, 8]),      # 64-point levels: 2^12 points, 64 columns
     (1 << 21, 8, [512, 4096], [8, 8]),       # writing rows 32 KB apart only: 2^12 points
     (1 << 22, 4, [1024, 4096], [8, 4]),
+    (1 << 21, 128, [512, 4096], [8, 16]),    # ... beyond the Infinity Cache: 128-byte runs, 2^13..2^14 points
+    (1 << 22, 64, [1024, 4096], [8, 16]),
+    (1 << 23, 32, [2048, 4096], [8, 8]),
+    (1 << 21, 16, [512, 4096], [8, 16]),     # 2^25 points
+    (1 << 22, 8, [1024, 4096], [8, 16]),
+    (1 << 23, 4, [2048, 4096], [8, 8]),
+    (1 << 30, 1, [1024, 1024, 1024], [16, 16, 16]),
     (1 << 24, 1, [4096, 4096], [8, 8]),      # paired columns
 ])
 def test_default_tile_widths(n, batch, lift, widths):
     """The planner's default tile of a complex64 level with a unit-stride
     tile side: at least 128-byte runs (a level that only writes along the
-    tile, rows 32 KB or more apart, keeps 2^12 points, 2^13 at 256 points
-    over 2^26 points or more), 512-byte runs where
+    tile, rows 32 KB or more apart, keeps 2^12 points; from 2^25 points
+    (2^26 at 256 points) 2^13 points and at least 128-byte runs up to 2^14
+    points), 512-byte runs where
     the rows read lie 16 KB or more apart and at least 2048 tiles of 2^14
     points remain."""
     h = capi.moa_fft_plan(n, batch, lift, flags=HOST)
@@ -529,10 +537,16 @@ def test_default_tile_widths(n, batch, lift, widths):
     (1 << 16, 128, [256, 256], [32, 8]),
     (1 << 22, 2, [2048, 2048], [4, 4]),
     (1 << 20, 8, [256, 4096], [2, 8]),       # write side only: 2^11 points
+    (1 << 22, 2, [1024, 4096], [2, 4]),      # ... 64-byte runs, up to 128 MiB
+    (1 << 22, 4, [1024, 4096], [2, 8]),      # from 256 MiB: 128-byte runs
+    (1 << 21, 8, [512, 4096], [2, 8]),
+    (1 << 23, 4, [2048, 4096], [2, 4]),      # (2^13 points at most)
+    (1 << 20, 32, [256, 4096], [2, 8]),
 ])
 def test_default_tile_widths_c128(n, batch, lift, widths):
     """Complex128 levels reading along a unit-stride tile side take the
-    largest tile (2^13 points); write-side tiles keep 2^11 points."""
+    largest tile (2^13 points); write-side tiles keep 2^11 points and 64-byte
+    runs, and 128-byte runs from 256 MiB at 512 .. 2048 points."""
     h = capi.moa_fft_plan(n, batch, lift, capi.MOA_C128, flags=HOST)
     try:
         d = json.loads(capi.moa_fft_describe(h))
