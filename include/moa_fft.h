@@ -156,12 +156,15 @@ typedef struct {
  * on the next axis outwards.  The product must equal n, every factor must
  * be a power of two, and each factor must fit one workgroup (at most 2^14
  * points for MOA_C64, 2^13 for MOA_C128).  NULL/0 selects a default lift
- * with the fewest levels (one level when n itself fits).  With a SPLIT
- * precision the default keeps that level count and, where it can, cuts the
- * levels into 16-, 256- and 4096-point levels for the matrix cores (2^20:
- * <4096 256>), leaving the bits that make no whole radix-16 digit to the
- * first level.  The paper's uniform blocking by c corresponds to
- * <2^p_max c ... c>.
+ * (measured on MI355X): one level when n itself fits; for MOA_C64 with
+ * 2^19 <= n <= 2^23 two levels with one of 4096 points, <n/4096 4096> while
+ * the batch holds 2^24 points or fewer (and always at 2^23), <4096 n/4096>
+ * beyond; for MOA_C64 with n >= 2^25 the three levels <256 4096 n/2^20>;
+ * otherwise the fewest levels of near-equal size.  With a SPLIT precision
+ * and n <= 2^24 the default takes the fewest levels, cut where it can into
+ * 16-, 256- and 4096-point levels for the matrix cores (2^20: <4096 256>),
+ * the bits that make no whole radix-16 digit going to the first level.  The
+ * paper's uniform blocking by c corresponds to <2^p_max c ... c>.
  *
  * On success *out receives a new plan.  Errors: MOA_ERR_NULL (out NULL, or
  * lift_shape NULL with lift_rank > 0), MOA_ERR_SIZE, MOA_ERR_LIFT,

@@ -1136,16 +1136,16 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
         const int L = d <= maxlg ? 1 : (d + maxlg - 1) / maxlg;
         // Level sizes in pass order (innermost level first); lift is the reverse.
         std::vector<int> parts;
-        if (prec != MOA_FFT_PREC_NATIVE) {
-            // Split precisions: the same number of levels (HBM passes) as
-            // in FP32, cut into whole radix-16 digits so that the levels run
+        if (prec != MOA_FFT_PREC_NATIVE && d <= 24) {
+            // Split precisions up to 2^24 points: the fewest levels (HBM
+            // passes), cut into whole radix-16 digits so that the levels run
             // on the matrix cores (2^4, 2^8 and 2^12 points).  The bits that
             // do not make a whole digit go to the first level, which runs in
             // FP32 and takes as few bits as the 12-bit levels after it allow.
             // The digits are spread evenly, the shorter levels first (2^20:
             // <4096 256>, 1.85-2.05 ms against 2.07-2.25 ms for <256 4096>
-            // on 256 transforms).  Where no such cut exists (2^27, 2^28:
-            // two levels of at most 2^14 points) the FP32 lift is kept.
+            // on 256 transforms).  From 2^25 points the FP32 default below,
+            // <256 4096 2^(d-20)>, already has two matrix-core levels.
             const int r = d % 4;
             const int f = r == 0 && d <= 12 * L ? 0 : std::max(r, d - 12 * (L - 1));
             const int k = f ? L - 1 : L;  // levels of whole digits
@@ -1154,6 +1154,27 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
                 if (f) parts.push_back(f);
                 for (int i = 0; i < k; ++i) parts.push_back(4 * (q / k + (i >= k - q % k ? 1 : 0)));
             }
+        }
+        if (parts.empty() && !fp64 && d >= 19 && d <= 23) {
+            // Complex64 FP32, 2^19 .. 2^23 points: two levels, one of 4096
+            // points (the paired-column level, 64-byte runs from 2^15-point
+            // tiles).  It runs first (<2^(d-12) 4096>) while the batch holds
+            // 2^24 points or fewer, last (<4096 2^(d-12)>) beyond, and first
+            // at 2^23 points either way.  Measured against the near-equal
+            // split, e.g. 16 x 2^20 0.110 against 0.138 ms, 4 x 2^22 0.129
+            // against 0.169 ms, 64 x 2^20 0.490 against 0.579 ms, 256 x
+            // 2^20 1.69 against 2.24 ms, 32 x 2^23 2.05 against 2.38 ms.
+            const bool first = d == 23 || n * batch <= (int64_t(1) << 24);
+            parts = first ? std::vector<int>{12, d - 12} : std::vector<int>{d - 12, 12};
+        }
+        if (parts.empty() && !fp64 && d >= 25) {
+            // Complex64 FP32, 2^25 points and more: three levels <256 4096
+            // 2^(d-20)> rather than two with 2^13- or 2^14-point levels,
+            // whose tiles read and write 16- or 32-byte runs: 2^25 0.315
+            // against 0.473 ms, 2^26 0.721 against 0.920 ms, 2^27 1.39
+            // against 1.84 ms, 2^28 2.96 against 4.12 ms, 2^29 5.86 against
+            // 6.93 ms (<1024 1024 512>), 2^30 13.8 against 14.7 ms.
+            parts = {d - 20, 12, 8};
         }
         if (parts.empty()) {
             // near-equal split, the outer levels take the remainder first

@@ -165,11 +165,25 @@ def describe(n, batch=1, lift=None, dtype=capi.MOA_C64, tuning=None, prec=capi.M
 
 def test_default_lifts():
     assert describe(1 << 24)["lift"] == [4096, 4096]
-    assert describe(1 << 20)["lift"] == [1024, 1024]
     assert describe(1 << 16)["lift"] == [256, 256]
+    assert describe(1 << 18)["lift"] == [512, 512]
     assert describe(1 << 14)["lift"] == [1 << 14]
+    # complex64, 2^19 .. 2^23 points: a 4096-point level, first while the
+    # batch holds 2^24 points or fewer, last beyond (first at 2^23 always)
+    assert describe(1 << 20)["lift"] == [256, 4096]
+    assert describe(1 << 20, batch=16)["lift"] == [256, 4096]
+    assert describe(1 << 20, batch=17)["lift"] == [4096, 256]
+    assert describe(1 << 22, batch=64)["lift"] == [4096, 1024]
+    assert describe(1 << 19, batch=128)["lift"] == [4096, 128]
+    assert describe(1 << 23, batch=32)["lift"] == [2048, 4096]
+    # 2^25 points and more: <256 4096 2^(d-20)>
+    assert describe(1 << 25)["lift"] == [256, 4096, 32]
+    assert describe(1 << 28)["lift"] == [256, 4096, 256]
+    assert describe(1 << 30)["lift"] == [256, 4096, 1024]
+    # complex128 keeps the near-equal split of the fewest levels
     assert describe(1 << 14, dtype=capi.MOA_C128)["lift"] == [128, 128]
-    assert describe(1 << 30)["lift"] == [1024, 1024, 1024]
+    assert describe(1 << 20, dtype=capi.MOA_C128)["lift"] == [1024, 1024]
+    assert describe(1 << 30, dtype=capi.MOA_C128)["lift"] == [1024, 1024, 1024]
     d = describe(1 << 24, lift=[4096, 4096])
     assert d["levels"] == [4096, 4096] and len(d["passes"]) == 2
     assert d["workspace_bytes"] == 8 << 24
@@ -181,17 +195,17 @@ def test_default_split_lifts_use_the_matrix_cores(prec):
     cuts the levels into whole radix-16 digits, shorter levels first, so that
     they run on the matrix cores; bits left over from whole digits go to the
     first level, the only one that stays in FP32, and it takes as few as the
-    12-bit levels after it allow.  2^27 and 2^28 have no such cut into two
-    levels and keep the FP32 lift."""
+    12-bit levels after it allow.  From 2^25 points the FP32 default
+    <256 4096 2^(d-20)> already has two matrix-core levels."""
     want = {12: [4096], 16: [256, 256], 20: [4096, 256], 24: [4096, 4096], 13: [8192], 14: [16384],
-            15: [4096, 8], 17: [4096, 32], 19: [4096, 128], 22: [4096, 1024], 25: [4096, 8192],
-            26: [4096, 16384], 27: [16384, 8192], 28: [16384, 16384], 29: [4096, 4096, 32],
-            30: [4096, 4096, 64]}
+            15: [4096, 8], 17: [4096, 32], 19: [4096, 128], 22: [4096, 1024], 25: [256, 4096, 32],
+            26: [256, 4096, 64], 27: [256, 4096, 128], 28: [256, 4096, 256], 29: [256, 4096, 512],
+            30: [256, 4096, 1024]}
     for lg in range(1, 31):
         d = describe(1 << lg, batch=64, prec=prec)
         native = describe(1 << lg, batch=64)
         assert len(d["passes"]) == len(native["passes"]), lg
-        assert lg in (4, 27, 28) or any(p["mfma"] != "none" for p in d["passes"]) or lg % 4 and lg < 15, lg
+        assert lg == 4 or any(p["mfma"] != "none" for p in d["passes"]) or lg % 4 and lg < 15, lg
     for lg, lift in want.items():
         d = describe(1 << lg, batch=4, prec=prec)
         assert d["lift"] == lift, lg
@@ -201,7 +215,7 @@ def test_default_split_lifts_use_the_matrix_cores(prec):
         for i, p in enumerate(d["passes"]):
             on_mfma = p["N"] in (16, 256, 4096)
             assert (p["mfma"] != "none") == on_mfma, (lg, i)
-            assert on_mfma or i == 0 or lg in (27, 28), (lg, i)
+            assert on_mfma or i == 0, (lg, i)
     # a length of at most 2^12 points stays one level; only 16, 256, 4096 use MFMA
     assert describe(1 << 11, batch=64, prec=prec)["lift"] == [2048]
     assert describe(1 << 8, batch=64, prec=prec)["passes"][0]["mfma"] != "none"
