@@ -1176,6 +1176,15 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
             // 6.93 ms (<1024 1024 512>), 2^30 13.8 against 14.7 ms.
             parts = {d - 20, 12, 8};
         }
+        if (parts.empty() && fp64 && d >= 23 && d <= 26) {
+            // Complex128, 2^23 .. 2^26 points: three levels <256 256
+            // 2^(d-16)> rather than two of 2^11 .. 2^13 points, whose tiles
+            // of at most 2^13 points hold one to four columns: 2^23 0.159
+            // against 0.208 ms, 4 x 2^23 0.646 against 0.871 ms, 8 x 2^24
+            // 2.38 against 3.46 ms, 2^25 0.665 against 1.12 ms, 2 x 2^26
+            // 2.53 against 4.29 ms.
+            parts = {d - 16, 8, 8};
+        }
         if (parts.empty()) {
             // near-equal split, the outer levels take the remainder first
             for (int i = L - 1; i >= 0; --i) parts.push_back(d / L + (i < d % L ? 1 : 0));

@@ -180,9 +180,14 @@ def test_default_lifts():
     assert describe(1 << 25)["lift"] == [256, 4096, 32]
     assert describe(1 << 28)["lift"] == [256, 4096, 256]
     assert describe(1 << 30)["lift"] == [256, 4096, 1024]
-    # complex128 keeps the near-equal split of the fewest levels
+    # complex128: the near-equal split of the fewest levels, but three
+    # levels <256 256 2^(d-16)> at 2^23 .. 2^26 points
     assert describe(1 << 14, dtype=capi.MOA_C128)["lift"] == [128, 128]
     assert describe(1 << 20, dtype=capi.MOA_C128)["lift"] == [1024, 1024]
+    assert describe(1 << 22, dtype=capi.MOA_C128)["lift"] == [2048, 2048]
+    assert describe(1 << 23, dtype=capi.MOA_C128)["lift"] == [256, 256, 128]
+    assert describe(1 << 26, dtype=capi.MOA_C128)["lift"] == [256, 256, 1024]
+    assert describe(1 << 27, dtype=capi.MOA_C128)["lift"] == [512, 512, 512]
     assert describe(1 << 30, dtype=capi.MOA_C128)["lift"] == [1024, 1024, 1024]
     d = describe(1 << 24, lift=[4096, 4096])
     assert d["levels"] == [4096, 4096] and len(d["passes"]) == 2
