@@ -8,7 +8,7 @@ transpose folded into the store).  A step is one full transform; inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
-                    [--extras uneven,fwd_adj,split_mfma,tuned,hypercube,c128]
+                    [--extras uneven,fwd_adj,split_mfma,tuned,hypercube,defaults,c128]
 
 Throughput is 5 n log2(n) / t (GFLOP/s).  The roofline block reports the
 dominant kernel (the slower of the two level launches, each timed in its place
@@ -18,7 +18,8 @@ element once per launch); `traffic` is the HBM bytes per launch that the
 rocprofv3 FETCH_SIZE / WRITE_SIZE counters measured for the same kernel
 source (profiles/traffic.json), or null when the kernel source has changed
 since.  The extras time the other workloads (uneven batch, forward+adjoint,
-split-precision matrix-core levels, the tuned lift, complex128 latency); the
+split-precision matrix-core levels, the tuned lift, the default lifts against
+the former near-equal ones, complex128 latency); the
 CPU leg times the FP64 oracle and states the error of every result against it.
 """
 from __future__ import annotations
@@ -533,6 +534,29 @@ def extras(args, torch, np, mfft, inputs):
         ex["hypercube_13_qubits_c64"] = rec
         del rho, tgt
 
+    if want("defaults"):
+        # The planner's default lifts where they depart from the fewest levels
+        # of near-equal size, each against that former default, whole
+        # transforms timed alike (median of three trials).
+        rec = {}
+        for n, B, dt, former in ((1 << 20, 256, torch.complex64, [1024, 1024]),
+                                 (1 << 28, 1, torch.complex64, [16384, 16384]),
+                                 (1 << 25, 1, torch.complex128, [8192, 4096])):
+            xd = inputs.device_uniform_complex(n * B, args.seed + 9, dt, dev)
+            yd = torch.empty_like(xd)
+            r = {}
+            for name, lift in (("default", None), ("near_equal", former)):
+                p = mfft.Plan(n, B, lift, dtype=dt)
+                p.forward(xd, out=yd)
+                ms = sorted(time_events(lambda: p.forward(xd, out=yd), max(3, reps // 2), torch)
+                            for _ in range(3))[1]
+                r[name] = {"lift": p.describe()["lift"], "ms": round(ms, 4)}
+                p.close()
+            r["speedup"] = round(r["near_equal"]["ms"] / r["default"]["ms"], 3)
+            rec["%s_2^%d_x%d" % ("c64" if dt == torch.complex64 else "c128", n.bit_length() - 1, B)] = r
+            del xd, yd
+        ex["default_lifts"] = rec
+
     if want("c128"):
         # Latency of the complex128 n = 2^10 transform (single workgroup).
         p = mfft.Plan(1 << 10, 1, None, dtype=torch.complex128)
@@ -758,7 +782,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and the error statement)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extra workloads: uneven, fwd_adj, split_mfma, tuned, nd, hypercube, c128 "
+                    help="comma list of extra workloads: uneven, fwd_adj, split_mfma, tuned, nd, hypercube, "
+                         "defaults, c128 "
                          "(default all)")
     ap.add_argument("--profile", default=None,
                     help="kernel-only run for rocprofv3: warm-up, then --steps launches of one workload's kernels "
