@@ -734,6 +734,13 @@ def profile_run(args, torch, np, mfft, inputs):
         lift = [4096, 256] if w.endswith("_4096x256") else [256, 4096]
         p = mfft.Plan(n, B, lift, prec="native" if prec == "split_native" else prec)
         fn = lambda: p.forward(x, out=y)  # noqa: E731
+    elif w == "default_2p28":
+        # one complex64 transform of 2^28 points under its default lift
+        n = 1 << 28
+        x = inputs.device_uniform_complex(n, args.seed + 9, torch.complex64, dev)
+        y = torch.empty_like(x)
+        p = mfft.Plan(n, 1, None)
+        fn = lambda: p.forward(x, out=y)  # noqa: E731
     elif w in ("nd2", "nd3"):
         dims = (4096, 4096) if w == "nd2" else (256, 256, 256)
         x = inputs.device_uniform_complex(1 << 24, args.seed + 5, torch.complex64, dev)
