@@ -40,7 +40,7 @@ def rows_err(got, want):
 @pytest.mark.parametrize("n,batch,lift", [(256, 64, None), (4096, 4, None), (1 << 16, 2, [16, 4096]),
                                           (1 << 16, 2, [256, 256]), (1 << 20, 2, [256, 4096]),
                                           (1 << 12, 3, [16, 256]), (1 << 20, 2, [4096, 256]),
-                                          (1 << 20, 16, None), (1 << 19, 16, None)])
+                                          (1 << 20, 16, None), (1 << 19, 16, None), (1 << 25, 1, None)])
 def test_split_matches_oracle(prec, n, batch, lift):
     need_gpu()
     x = inputs.uniform_complex((batch, n), seed=n + batch, dtype=np.complex64)
