@@ -281,6 +281,11 @@ def check_pass(p, total, elem_bytes):
     (4096, 1, None, capi.MOA_C128), (2048, 1, None, capi.MOA_C128), (256, 1, None, capi.MOA_C64),
     (512, 1, None, capi.MOA_C128), (16, 2048, None, capi.MOA_C64), (1024, 7, None, capi.MOA_C128),
     (4096, 128, None, capi.MOA_C64),
+    # default lifts and wide far-writing tiles beyond the Infinity Cache
+    (1 << 20, 1, None, capi.MOA_C64), (1 << 20, 17, None, capi.MOA_C64), (1 << 25, 1, None, capi.MOA_C64),
+    (1 << 23, 1, None, capi.MOA_C128), (1 << 22, 8, [1024, 4096], capi.MOA_C64),
+    (1 << 21, 16, [512, 4096], capi.MOA_C64), (1 << 23, 4, [2048, 4096], capi.MOA_C64),
+    (1 << 22, 4, [1024, 4096], capi.MOA_C128),
 ])
 def test_pass_kernel_geometry(n, batch, lift, dtype):
     h = capi.moa_fft_plan(n, batch, lift, dtype=dtype, flags=HOST)
