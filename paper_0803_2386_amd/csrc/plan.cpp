@@ -1155,17 +1155,22 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
                 for (int i = 0; i < k; ++i) parts.push_back(4 * (q / k + (i >= k - q % k ? 1 : 0)));
             }
         }
-        if (parts.empty() && !fp64 && d >= 19 && d <= 23) {
-            // Complex64 FP32, 2^19 .. 2^23 points: two levels, one of 4096
-            // points (the paired-column level, 64-byte runs from 2^15-point
-            // tiles).  It runs first (<2^(d-12) 4096>) while the batch holds
-            // 2^24 points or fewer, last (<4096 2^(d-12)>) beyond, and first
-            // at 2^23 points either way.  Measured against the near-equal
-            // split, e.g. 16 x 2^20 0.110 against 0.138 ms, 4 x 2^22 0.129
-            // against 0.169 ms, 64 x 2^20 0.490 against 0.579 ms, 256 x
-            // 2^20 1.69 against 2.24 ms, 32 x 2^23 2.05 against 2.38 ms.
-            const bool first = d == 23 || n * batch <= (int64_t(1) << 24);
-            parts = first ? std::vector<int>{12, d - 12} : std::vector<int>{d - 12, 12};
+        if (parts.empty() && !fp64 && d >= 19 && d <= 23 && n * batch >= (int64_t(1) << 24)) {
+            // Complex64 FP32, 2^19 .. 2^23 points, batches of 2^24 points or
+            // more: two levels, one of 4096 points (the paired-column level,
+            // 64-byte runs from 2^15-point tiles).  It runs first (<2^(d-12)
+            // 4096>) while the batch holds 2^25 points or fewer, last (<4096
+            // 2^(d-12)>) beyond, and first at 2^23 points either way.
+            // Measured against the near-equal split, e.g. 16 x 2^20 0.110
+            // against 0.138 ms, 4 x 2^22 0.129 against 0.169 ms, 32 x 2^20
+            // 0.219 against 0.278 ms (<4096 256>: 0.277), 64 x 2^20 0.490
+            // against 0.579 ms (<256 4096>: 0.513), 256 x 2^20 1.69 against
+            // 2.24 ms, 32 x 2^23 2.05 against 2.38 ms.  Smaller batches keep
+            // the near-equal split (a 4096-point level has too few of its
+            // one-per-CU tiles there: 2^22 0.053 against 0.041 ms, 8 x 2^19
+            // 0.046 against 0.035 ms).
+            const bool fits = n * batch <= (int64_t(1) << 25);
+            parts = (d == 23 || fits) ? std::vector<int>{12, d - 12} : std::vector<int>{d - 12, 12};
         }
         if (parts.empty() && !fp64 && d >= 25) {
             // Complex64 FP32, 2^25 points and more: three levels <256 4096

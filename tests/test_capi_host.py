@@ -166,16 +166,20 @@ def describe(n, batch=1, lift=None, dtype=capi.MOA_C64, tuning=None, prec=capi.M
 def test_default_lifts():
     assert describe(1 << 24)["lift"] == [4096, 4096]
     assert describe(1 << 16)["lift"] == [256, 256]
-    assert describe(1 << 18)["lift"] == [512, 512]
     assert describe(1 << 14)["lift"] == [1 << 14]
-    # complex64, 2^19 .. 2^23 points: a 4096-point level, first while the
-    # batch holds 2^24 points or fewer, last beyond (first at 2^23 always)
-    assert describe(1 << 20)["lift"] == [256, 4096]
+    # complex64, 2^19 .. 2^23 points in batches of 2^24 points or more: a
+    # 4096-point level, first up to 2^25 points a batch, last beyond (first
+    # at 2^23 always); smaller batches keep the near-equal split
+    assert describe(1 << 20)["lift"] == [1024, 1024]
+    assert describe(1 << 20, batch=15)["lift"] == [1024, 1024]
     assert describe(1 << 20, batch=16)["lift"] == [256, 4096]
-    assert describe(1 << 20, batch=17)["lift"] == [4096, 256]
+    assert describe(1 << 20, batch=32)["lift"] == [256, 4096]
+    assert describe(1 << 20, batch=33)["lift"] == [4096, 256]
     assert describe(1 << 22, batch=64)["lift"] == [4096, 1024]
     assert describe(1 << 19, batch=128)["lift"] == [4096, 128]
+    assert describe(1 << 23)["lift"] == [4096, 2048]
     assert describe(1 << 23, batch=32)["lift"] == [2048, 4096]
+    assert describe(1 << 18, batch=128)["lift"] == [512, 512]
     # 2^25 points and more: <256 4096 2^(d-20)>
     assert describe(1 << 25)["lift"] == [256, 4096, 32]
     assert describe(1 << 28)["lift"] == [256, 4096, 256]

@@ -115,23 +115,23 @@ def test_closed_forms_on_gpu():
         assert np.abs(got - want).max() < 2e-6 * np.log2(n) * np.sqrt(n) * 4
 
 
-@pytest.mark.parametrize("n,dtype,lift", [(1 << 20, torch.complex64, [256, 4096]),
-                                          (1 << 25, torch.complex64, [256, 4096, 32]),
-                                          (1 << 23, torch.complex128, [256, 256, 128])])
-def test_default_lifts_on_the_full_vector(n, dtype, lift):
+@pytest.mark.parametrize("n,batch,dtype,lift", [(1 << 20, 16, torch.complex64, [256, 4096]),
+                                                (1 << 25, 1, torch.complex64, [256, 4096, 32]),
+                                                (1 << 23, 1, torch.complex128, [256, 256, 128])])
+def test_default_lifts_on_the_full_vector(n, batch, dtype, lift):
     """The measured default lifts (a 4096-point level for complex64 at 2^19
-    .. 2^23 points, <256 4096 n/2^20> from 2^25, <256 256 n/2^16> for
-    complex128 at 2^23 .. 2^26) on the whole vector, both directions, against
-    the oracle."""
+    .. 2^23 points in batches of 2^24 points or more, <256 4096 n/2^20> from
+    2^25, <256 256 n/2^16> for complex128 at 2^23 .. 2^26) on every element,
+    both directions, against the oracle."""
     need_gpu()
     dev = torch.device("cuda", 0)
-    x = inputs.device_uniform_complex(n, 19, dtype, dev)
-    plan = mfft.Plan(n, 1, None, dtype=dtype)
+    x = inputs.device_uniform_complex(n * batch, 19, dtype, dev)
+    plan = mfft.Plan(n, batch, None, dtype=dtype)
     assert plan.describe()["lift"] == lift
-    xr = x.cpu().numpy().astype(np.complex128)
+    xr = x.cpu().numpy().astype(np.complex128).reshape(batch, n)
     for name, sign, fn in (("forward", -1, plan.forward), ("adjoint", 1, plan.adjoint)):
-        got = fn(x).cpu().numpy().astype(np.complex128)
-        err = rel_err_rows(got, oracle.fft(xr, sign))
+        got = fn(x).cpu().numpy().astype(np.complex128).reshape(batch, n)
+        err = rel_err_rows(got, oracle.fft_batch(xr, sign, threads=8))
         print(f"default lift {lift} {dtype} {name}: rel err {err:.3e}", flush=True)
         assert err <= tol(n, dtype)
     plan.close()
