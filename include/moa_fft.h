@@ -159,8 +159,9 @@ typedef struct {
  * (measured on MI355X): one level when n itself fits; for MOA_C64 with
  * 2^19 <= n <= 2^23 in batches of 2^24 points or more, two levels with one
  * of 4096 points, <n/4096 4096> while the batch holds 2^25 points or fewer
- * (and always at 2^23), <4096 n/4096> beyond; for MOA_C64 with n >= 2^25
- * the three levels <256 4096 n/2^20>;
+ * (and always at 2^23), <4096 n/4096> beyond, except <256 128 256> for
+ * n = 2^23 in batches of up to 2^25 points; for MOA_C64 with n >= 2^25 the
+ * three levels <256 4096 n/2^20>;
  * for MOA_C128 with 2^23 <= n <= 2^26 the three levels <256 256 n/2^16>;
  * otherwise the fewest levels of near-equal size.  With a SPLIT precision
  * and n <= 2^24 the default takes the fewest levels, cut where it can into

@@ -1155,6 +1155,13 @@ moa_status_t moa_fft_plan_tuned(moa_fft_plan_t* out, int64_t n, int64_t batch, c
                 for (int i = 0; i < k; ++i) parts.push_back(4 * (q / k + (i >= k - q % k ? 1 : 0)));
             }
         }
+        if (parts.empty() && !fp64 && d == 23 && n * batch <= (int64_t(1) << 25)) {
+            // Complex64 FP32, 2^23 points in batches of up to 2^25 points:
+            // three levels <256 128 256>, 0.073 / 0.142 / 0.298 ms against
+            // 0.075 / 0.158 / 0.365 ms for two (1, 2, 4 transforms); 8
+            // transforms take the two levels below (0.660 against 0.676 ms).
+            parts = {8, 7, 8};
+        }
         if (parts.empty() && !fp64 && d >= 19 && d <= 23 && n * batch >= (int64_t(1) << 24)) {
             // Complex64 FP32, 2^19 .. 2^23 points, batches of 2^24 points or
             // more: two levels, one of 4096 points (the paired-column level,

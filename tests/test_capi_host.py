@@ -177,8 +177,11 @@ def test_default_lifts():
     assert describe(1 << 20, batch=33)["lift"] == [4096, 256]
     assert describe(1 << 22, batch=64)["lift"] == [4096, 1024]
     assert describe(1 << 19, batch=128)["lift"] == [4096, 128]
-    assert describe(1 << 23)["lift"] == [4096, 2048]
     assert describe(1 << 23, batch=32)["lift"] == [2048, 4096]
+    assert describe(1 << 23, batch=8)["lift"] == [2048, 4096]
+    # 2^23 points in batches of up to 2^25 points: three levels
+    assert describe(1 << 23)["lift"] == [256, 128, 256]
+    assert describe(1 << 23, batch=4)["lift"] == [256, 128, 256]
     assert describe(1 << 18, batch=128)["lift"] == [512, 512]
     # 2^25 points and more: <256 4096 2^(d-20)>
     assert describe(1 << 25)["lift"] == [256, 4096, 32]

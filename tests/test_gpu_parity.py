@@ -116,11 +116,13 @@ def test_closed_forms_on_gpu():
 
 
 @pytest.mark.parametrize("n,batch,dtype,lift", [(1 << 20, 16, torch.complex64, [256, 4096]),
+                                                (1 << 23, 2, torch.complex64, [256, 128, 256]),
                                                 (1 << 25, 1, torch.complex64, [256, 4096, 32]),
                                                 (1 << 23, 1, torch.complex128, [256, 256, 128])])
 def test_default_lifts_on_the_full_vector(n, batch, dtype, lift):
     """The measured default lifts (a 4096-point level for complex64 at 2^19
-    .. 2^23 points in batches of 2^24 points or more, <256 4096 n/2^20> from
+    .. 2^23 points in batches of 2^24 points or more, <256 128 256> for 2^23
+    points in batches of up to 2^25 points, <256 4096 n/2^20> from
     2^25, <256 256 n/2^16> for complex128 at 2^23 .. 2^26) on every element,
     both directions, against the oracle."""
     need_gpu()

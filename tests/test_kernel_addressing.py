@@ -283,6 +283,7 @@ def check_pass(p, total, elem_bytes):
     (4096, 128, None, capi.MOA_C64),
     # default lifts and wide far-writing tiles beyond the Infinity Cache
     (1 << 20, 1, None, capi.MOA_C64), (1 << 20, 17, None, capi.MOA_C64), (1 << 25, 1, None, capi.MOA_C64),
+    (1 << 23, 2, None, capi.MOA_C64),
     (1 << 23, 1, None, capi.MOA_C128), (1 << 22, 8, [1024, 4096], capi.MOA_C64),
     (1 << 21, 16, [512, 4096], capi.MOA_C64), (1 << 23, 4, [2048, 4096], capi.MOA_C64),
     (1 << 22, 4, [1024, 4096], capi.MOA_C128),
