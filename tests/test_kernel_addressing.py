@@ -559,3 +559,36 @@ def test_default_tile_widths_c128(n, batch, lift, widths):
     finally:
         capi.moa_fft_destroy(h)
     assert [p["tile_width"] for p in d["passes"]] == widths
+
+
+@pytest.mark.parametrize("n,batch,lift", [(1 << 20, 16, [1024, 1024]), (1 << 16, 256, [256, 256]),
+                                          (1 << 24, 1, [256, 256, 256]), (1 << 22, 64, [1024, 4096]),
+                                          (1 << 21, 8, [512, 4096])])
+def test_store_readback_across_columns_is_bank_conflict_free(n, batch, lift):
+    """A level that reads along its columns and stores along its tile (up to
+    16 columns, 16 or more threads a column) reads the LDS back across the
+    columns before the store: lane t takes column t mod W, row t / W + m TPC.
+    Each run of 16 lanes (one LDS cycle of 8-byte accesses) lands on 16
+    distinct bank pairs with the planned column stride."""
+    h = capi.moa_fft_plan(n, batch, lift, flags=HOST)
+    try:
+        d = json.loads(capi.moa_fft_describe(h))
+    finally:
+        capi.moa_fft_destroy(h)
+    seen = 0
+    for p in d["passes"]:
+        W, N = p["tile_width"], p["N"]
+        if p["in_tile_fast"] or not p["out_tile_fast"] or p["kernel_mode"] not in (0, 1, 2) or W > 16:
+            continue
+        TPC = N // p["points_per_thread"]
+        if TPC < 16:
+            continue
+        seen += 1
+        cs, lgw = p["lds_col_stride"], W.bit_length() - 1
+        t = np.arange(p["threads"])
+        wst, jst = t & (W - 1), t >> lgw
+        for m in range(p["points_per_thread"]):
+            slots = wst * cs + np.array([pad(int(r)) for r in jst + m * TPC])
+            for c in range(0, len(t), 16):
+                assert len(set((slots[c:c + 16] % 16).tolist())) == 16, (p["level"], m, c)
+    assert seen >= 1
