@@ -185,8 +185,10 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         // instead (a stride of 16 slots put all 16 lanes of a cycle on one
         // bank pair): <1024 1024> x 16 0.129 against 0.134 ms, <1024 4096>
         // x 64 1.97 against 2.06 ms, <256 256 256> 0.141 against 0.144 ms.
-        // (32 columns of 256 points ran 1 % slower so.)
-        if (!tile_fast && out_tf && lgw > 0 && lgw <= 4 && tpc_for(lgw) >= 16) lanes = W >= 16 ? 1 : 16 / W;
+        // (32 columns of 256 points ran 1 % slower so; complex128 levels,
+        // 16-byte lanes, showed no difference and keep the former stride.)
+        if (!fp64 && !tile_fast && out_tf && lgw > 0 && lgw <= 4 && tpc_for(lgw) >= 16)
+            lanes = W >= 16 ? 1 : 16 / W;
         const int cs = moa::lds_col_stride(1 << lgn, lanes);
         return std::make_pair(cs, W * cs * eb + table_bytes);
     };
