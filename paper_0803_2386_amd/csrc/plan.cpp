@@ -324,7 +324,13 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         if (!fp64 && in_tf) {
             int64_t points = int64_t(1) << lgn;
             for (int i = 0; i < d.nd; ++i) points *= d.size[i];
-            if (d.in_s_e * int64_t(eb) >= 16384 && (points >> 14) >= 2048)
+            // (Also a 256-point level whose rows lie closer, over 2^26 points
+            // or more: 1024 x 2^16 <256 256> 0.441 against 0.469 ms, 4096 x
+            // 2^16 1.73 against 1.91 ms, 16 x 2^24 <256 256 256> 2.57 against
+            // 2.79 ms, the 3-D 256^3 x 16 2.50 against 2.72 ms; 512-point
+            // levels gained in 3-D and lost in 1-D, so they keep the rule.)
+            const bool wide_rows = d.in_s_e * int64_t(eb) >= 16384 || (lgn == 8 && points >= (int64_t(1) << 26));
+            if (wide_rows && (points >> 14) >= 2048)
                 target_lg = std::max(target_lg, std::min(14, lgn + 6));
         }
         // Complex128 levels reading along a unit-stride tile side take the

@@ -77,6 +77,28 @@ def test_nd_headline_shapes_full_vector(dims):
     plan.close()
 
 
+def test_nd_256_cubed_batch_of_four_wide_tiles():
+    """Four 256^3 transforms (2^26 points: the 256-point axes take 64-column
+    tiles): two seeded batch entries of each direction against the oracle."""
+    need_gpu()
+    dims, B = (256, 256, 256), 4
+    N = int(np.prod(dims))
+    dev = torch.device("cuda", 0)
+    x = inputs.device_uniform_complex(N * B, 44, torch.complex64, dev)
+    plan = mfft.NDPlan(dims, B)
+    assert [p["tile_width"] for p in plan.describe()["passes"]] == [16, 64, 64]
+    for sign, fn in ((-1, plan.forward), (1, plan.adjoint)):
+        y = fn(x)
+        for b in (0, 3):
+            xb = x[b * N:(b + 1) * N].cpu().numpy().astype(np.complex128).reshape(dims)
+            want = oracle.fftn(xb, 3, sign)
+            err = rel_err_rows(y[b * N:(b + 1) * N].cpu().numpy(), want, 1)
+            print(f"nd 256^3 x4 entry {b} sign {sign} err={err:.3e}", flush=True)
+            assert err <= tol(N, torch.complex64)
+        del y
+    plan.close()
+
+
 def test_nd_in_place_levels_and_closed_form():
     need_gpu()
     dims = (64, 256)

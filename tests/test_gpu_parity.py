@@ -115,6 +115,26 @@ def test_closed_forms_on_gpu():
         assert np.abs(got - want).max() < 2e-6 * np.log2(n) * np.sqrt(n) * 4
 
 
+def test_wide_read_tiles_beyond_the_infinity_cache():
+    """1024 transforms of 2^16 points (2^26 points): the first 256-point
+    level reads 64-column tiles (rows 2 KB apart); four seeded rows of each
+    direction against the oracle."""
+    need_gpu()
+    n, batch = 1 << 16, 1024
+    dev = torch.device("cuda", 0)
+    x = inputs.device_uniform_complex(n * batch, 26, torch.complex64, dev)
+    plan = mfft.Plan(n, batch, None)
+    assert [p["tile_width"] for p in plan.describe()["passes"]] == [64, 16]
+    rows = torch.from_numpy(np.random.default_rng(26).choice(batch, 4, replace=False)).to(dev)
+    xr = x.view(batch, n)[rows].cpu().numpy().astype(np.complex128)
+    for name, sign, fn in (("forward", -1, plan.forward), ("adjoint", 1, plan.adjoint)):
+        got = fn(x).view(batch, n)[rows].cpu().numpy().astype(np.complex128)
+        err = rel_err_rows(got, oracle.fft_batch(xr, sign, threads=8))
+        print(f"1024 x 2^16 {name}: rel err {err:.3e}", flush=True)
+        assert err <= tol(n, torch.complex64)
+    plan.close()
+
+
 @pytest.mark.parametrize("n,batch,dtype,lift", [(1 << 20, 16, torch.complex64, [256, 4096]),
                                                 (1 << 23, 2, torch.complex64, [256, 128, 256]),
                                                 (1 << 25, 1, torch.complex64, [256, 4096, 32]),

@@ -500,11 +500,13 @@ def test_mfma_pair_lds_banks(n, lift):
     # read lie 32 KB apart and 2^28 points leave 16384 tiles of 2^14
     (1 << 16, 256, [256, 256], [16, 16]),
     (1 << 20, 256, [4096, 256], [64, 8]),
+    (1 << 16, 1024, [256, 256], [64, 16]),   # rows 2 KB apart, 2^26 points: 64 columns too
+    (1 << 18, 256, [512, 512], [16, 16]),    # (512-point levels keep 16)
     (1 << 20, 16, [4096, 256], [16, 8]),     # 2^24 points: 1024 tiles of 2^14, too few
     (1 << 20, 256, [256, 4096], [8, 32]),    # rows written 32 KB apart, 2^28 points: 32 columns
     (1 << 20, 32, [256, 4096], [8, 16]),     # 256 points: 32 columns from 2^26 points only
     (1 << 24, 1, [256, 256, 256], [16, 16, 16]),
-    (1 << 24, 4, [256, 256, 256], [64, 16, 32]),
+    (1 << 24, 4, [256, 256, 256], [64, 64, 32]),
     # 1024- and 2048-point levels: 128-byte runs up to 2^14 points a tile
     (1 << 20, 16, [1024, 1024], [16, 16]),
     (1 << 22, 4, [2048, 2048], [8, 8]),
@@ -527,8 +529,8 @@ def test_default_tile_widths(n, batch, lift, widths):
     tile, rows 32 KB or more apart, keeps 2^12 points; from 2^25 points
     (2^26 at 256 points) 2^13 points and at least 128-byte runs up to 2^14
     points), 512-byte runs where
-    the rows read lie 16 KB or more apart and at least 2048 tiles of 2^14
-    points remain."""
+    the rows read lie 16 KB or more apart (or, at 256 points, once the level
+    holds 2^26 points) and at least 2048 tiles of 2^14 points remain."""
     h = capi.moa_fft_plan(n, batch, lift, flags=HOST)
     try:
         d = json.loads(capi.moa_fft_describe(h))
@@ -592,3 +594,16 @@ def test_store_readback_across_columns_is_bank_conflict_free(n, batch, lift):
             for c in range(0, len(t), 16):
                 assert len(set((slots[c:c + 16] % 16).tolist())) == 16, (p["level"], m, c)
     assert seen >= 1
+
+
+def test_nd_axis_tiles_widen_beyond_the_infinity_cache():
+    """The 256-point axes of a 3-D transform of 2^26 points read 512-byte
+    runs (64 columns) like the one-dimensional levels; below 2^26 points
+    they keep 128-byte runs."""
+    for batch, want in ((4, [16, 64, 64]), (1, [16, 16, 16])):
+        h = capi.moa_fft_plan_nd([256, 256, 256], batch, flags=HOST)
+        try:
+            d = json.loads(capi.moa_fft_describe(h))
+        finally:
+            capi.moa_fft_destroy(h)
+        assert [p["tile_width"] for p in d["passes"]] == want, batch
