@@ -309,18 +309,21 @@ moa_status_t finish_pass(PassDesc& d, bool fp64, int want_w, int cus)
         // 2^24 points: the narrower tiles stay faster, <512 4096> 0.122
         // against 0.128 ms, <1024 4096> 0.131 against 0.142 ms.  Complex128
         // levels of 512 .. 2048 points take 128-byte runs (8 columns) up to
-        // 2^13 points from 256 MiB: 2^24 points <512 4096> 0.333 against
-        // 0.392 ms, <1024 4096> 0.353 against 0.383 ms, 2^25 points 0.667 /
-        // 0.694 against 0.759 / 0.781 ms; at 2^23 points they tie.)
+        // 2^13 points from 256 MiB, see below: 2^24 points <512 4096> 0.333
+        // against 0.392 ms, <1024 4096> 0.353 against 0.383 ms, 2^25 points
+        // 0.667 / 0.694 against 0.759 / 0.781 ms; at 2^23 points they tie.)
         const bool far_writes = !in_tf && out_tf && d.out_s_k * int64_t(eb) >= 32768;
         if (!fp64 && (in_tf || out_tf) && !far_writes) target_lg = std::max(target_lg, lgn + 4);
-        if (far_writes && lgn >= 8 && lgn <= 11) {
-            int64_t bytes = (int64_t(1) << lgn) * eb;
-            for (int i = 0; i < d.nd; ++i) bytes *= d.size[i];
-            if (!fp64 && bytes >= (int64_t(1) << (lgn == 8 ? 29 : 28)))
-                target_lg = std::max(target_lg, std::min(14, std::max(13, lgn + 4)));
-            if (fp64 && lgn >= 9 && bytes >= (int64_t(1) << 28)) target_lg = std::max(target_lg, std::min(13, lgn + 3));
-        }
+        int64_t level_bytes = (int64_t(1) << lgn) * eb;
+        for (int i = 0; i < d.nd; ++i) level_bytes *= d.size[i];
+        if (!fp64 && far_writes && lgn >= 8 && lgn <= 11 && level_bytes >= (int64_t(1) << (lgn == 8 ? 29 : 28)))
+            target_lg = std::max(target_lg, std::min(14, std::max(13, lgn + 4)));
+        // Complex128 write-side tiles of 512 .. 2048 points take 128-byte
+        // runs from 256 MiB whatever the row spacing: 2^26 points <512 512>
+        // 0.853 against 1.010 ms, <1024 1024> 0.915 against 1.056 ms (at
+        // 2^23 points 4 columns stay faster, 0.135 against 0.137 ms).
+        if (fp64 && !in_tf && out_tf && lgn >= 9 && lgn <= 11 && level_bytes >= (int64_t(1) << 28))
+            target_lg = std::max(target_lg, std::min(13, lgn + 3));
         if (!fp64 && in_tf) {
             int64_t points = int64_t(1) << lgn;
             for (int i = 0; i < d.nd; ++i) points *= d.size[i];

@@ -115,6 +115,28 @@ def test_closed_forms_on_gpu():
         assert np.abs(got - want).max() < 2e-6 * np.log2(n) * np.sqrt(n) * 4
 
 
+@pytest.mark.parametrize("n,batch,lift", [(1 << 20, 64, [1024, 1024]), (1 << 18, 256, [512, 512])])
+def test_complex128_write_side_tiles_beyond_the_infinity_cache(n, batch, lift):
+    """Complex128, 1 GiB: the last level writes along 8-column tiles (128-byte
+    runs) with its rows 8 or 16 KB apart; three seeded rows of each direction
+    against the oracle."""
+    need_gpu()
+    dev = torch.device("cuda", 0)
+    x = inputs.device_uniform_complex(n * batch, 27, torch.complex128, dev)
+    plan = mfft.Plan(n, batch, lift, dtype=torch.complex128)
+    assert plan.describe()["passes"][-1]["tile_width"] == 8
+    rows = torch.from_numpy(np.random.default_rng(n).choice(batch, 3, replace=False)).to(dev)
+    xr = x.view(batch, n)[rows].cpu().numpy()
+    for name, sign, fn in (("forward", -1, plan.forward), ("adjoint", 1, plan.adjoint)):
+        got = fn(x).view(batch, n)[rows].cpu().numpy()
+        err = rel_err_rows(got, oracle.fft_batch(xr, sign, threads=8))
+        print(f"c128 {batch} x {n} {lift} {name}: rel err {err:.3e}", flush=True)
+        assert err <= tol(n, torch.complex128)
+    plan.close()
+    del x
+    torch.cuda.empty_cache()
+
+
 def test_wide_read_tiles_beyond_the_infinity_cache():
     """1024 transforms of 2^16 points (2^26 points): the first 256-point
     level reads 64-column tiles (rows 2 KB apart); four seeded rows of each

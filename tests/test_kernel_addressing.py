@@ -550,11 +550,15 @@ def test_default_tile_widths(n, batch, lift, widths):
     (1 << 21, 8, [512, 4096], [2, 8]),
     (1 << 23, 4, [2048, 4096], [2, 4]),      # (2^13 points at most)
     (1 << 20, 32, [256, 4096], [2, 8]),
+    (1 << 18, 256, [512, 512], [16, 8]),     # rows 8 KB apart, 1 GiB: 128-byte runs too
+    (1 << 20, 64, [1024, 1024], [8, 8]),
+    (1 << 20, 8, [1024, 1024], [8, 4]),      # 128 MiB: 64-byte runs
 ])
 def test_default_tile_widths_c128(n, batch, lift, widths):
     """Complex128 levels reading along a unit-stride tile side take the
     largest tile (2^13 points); write-side tiles keep 2^11 points and 64-byte
-    runs, and 128-byte runs from 256 MiB at 512 .. 2048 points."""
+    runs, and 128-byte runs from 256 MiB at 512 .. 2048 points, whatever the
+    spacing of the rows they write."""
     h = capi.moa_fft_plan(n, batch, lift, capi.MOA_C128, flags=HOST)
     try:
         d = json.loads(capi.moa_fft_describe(h))
